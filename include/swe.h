@@ -1,0 +1,236 @@
+/*
+ * swe.h - C ABI of the MI355X (gfx950) library for adjoint-guided refinement
+ * flagging in shallow-water tsunami modelling.
+ *
+ * Method: Davis & LeVeque, "Adjoint methods for guiding adaptive mesh
+ * refinement in tsunami modeling".  The library implements the data-parallel
+ * hot path of that method:
+ *   - the 2D shallow-water finite-volume step of eq. (swe) (Sec. 5), in
+ *     wave-propagation form: f-wave Roe solver with the bathymetry source
+ *     folded into the flux difference, MC-limited second-order corrections,
+ *     transverse splitting of fluctuations, a dry-cell threshold and the CFL
+ *     number of the step;
+ *   - the 1D linearized equations of eqs. (swe_1d_linearized)/(hyp_linear);
+ *   - the time-reversed adjoint q~_t - (A^T q~)_x = 0 (Sec. 4) in 1D and its
+ *     2D form for A1, A2 of eq. (2d_hyperbolicsystem) (Sec. 5), with zero
+ *     normal velocity at walls and wet/dry interfaces;
+ *   - the snapshot window of eq. (ip_timerange) and the per-cell flag
+ *     max_k |q^T q^_k| > tol of Secs. 4.1-4.2 with the wet/dry rule of Sec. 6;
+ *   - the two-phase driver of Sec. 4 (adjoint snapshots, then the forward run
+ *     with flagging).
+ *
+ * Conventions (all entry points):
+ *   - Arithmetic is IEEE binary64 without fused multiply-add contraction.
+ *   - Device buffers are plain device pointers allocated by the caller (the
+ *     library never allocates or frees device memory).  A 2D field is one
+ *     plane of ny rows of `pitch` doubles (pitch >= nx), x fastest, no ghost
+ *     cells; cell (i, j) is at offset j*pitch + i and has centre
+ *     (x_lo + (i+1/2) dx, y_lo + (j+1/2) dy).  Boundary ghost cells are
+ *     synthesised by the kernels from the boundary conditions.
+ *   - ny == 1 selects the one-dimensional scheme (linear model and adjoint).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
+ *     the call returns without waiting, except where stated.  Buffers must
+ *     stay valid until the work has completed.
+ *   - Return value: SWE_OK or a negative swe_status.  Argument errors are
+ *     detected before anything is enqueued and leave all buffers untouched;
+ *     swe_last_error() then returns a message (per calling thread).
+ *   - Calls are reentrant and thread-safe for distinct buffers and streams.
+ */
+#ifndef SWE_H
+#define SWE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWE_API __attribute__((visibility("default")))
+
+typedef enum {
+    SWE_OK = 0,
+    SWE_E_INVAL = -1,      /* bad argument (null pointer, size, dt, alias, ...) */
+    SWE_E_CFL = -2,        /* the driver could not find an accepted step */
+    SWE_E_HIP = -3,        /* a HIP runtime call failed */
+    SWE_E_NOMEM = -4,      /* the caller's workspace is too small */
+    SWE_E_NONFINITE = -5,  /* a non-finite value appeared in the state */
+    SWE_E_NEGDEPTH = -6    /* a negative depth had to be clamped */
+} swe_status;
+
+typedef enum { SWE_BC_WALL = 0, SWE_BC_EXTRAP = 1 } swe_bc;
+typedef enum { SWE_NONLINEAR = 0, SWE_LINEAR = 1 } swe_model;
+typedef enum { SWE_TARGET_GAUSS = 0, SWE_TARGET_DISK = 1 } swe_target_shape;
+
+/* Uniform grid.  ny == 1: one space dimension.  nx >= 2 and (ny == 1 or ny >= 2). */
+typedef struct {
+    int32_t nx, ny;
+    int32_t pitch;          /* doubles between consecutive rows, >= nx */
+    int32_t bc[4];          /* swe_bc for the x_lo, x_hi, y_lo, y_hi sides */
+    double dx, dy;          /* cell sizes (m) */
+    double x_lo, y_lo;      /* lower-left corner (m) */
+} swe_grid;
+
+typedef struct {
+    int32_t model;          /* swe_model of the forward problem */
+    int32_t order;          /* 1 (Godunov) or 2 (MC-limited corrections) */
+    int32_t transverse;     /* 1: transverse splitting of fluctuations (2D) */
+    int32_t reserved;
+    double g;               /* gravity (m/s^2) */
+    double sea_level;       /* eta_bar: the surface the equations are linearized about */
+    double dry_tol;         /* a cell is wet iff its depth > dry_tol (m) */
+    double cfl_desired;     /* target Courant number of the variable time step */
+    double cfl_max;         /* steps with a larger Courant number are rejected */
+} swe_params;
+
+/* Three device planes.  Nonlinear: (h, hu, hv).  Linear and adjoint:
+ * (eta, mu, gamma) - in 1D only f0, f1 are used. */
+typedef struct { double *f0, *f1, *f2; } swe_fields;
+
+/* Device-resident per-step outputs.  The step kernels max-reduce the Courant
+ * number into cfl_bits (the bit pattern of a non-negative double, so integer
+ * max is float max) and count clamped negative depths and non-finite results;
+ * the caller zeroes the struct before the steps it wants to observe. */
+typedef struct {
+    uint64_t cfl_bits;
+    int32_t n_clamped;
+    int32_t n_nonfinite;
+} swe_scalars;
+
+/*
+ * swe_step - one forward finite-volume step of length dt.
+ * Nonlinear model (2D): eq. (swe) of Sec. 5 by the f-wave Roe solver; wet iff
+ * h > dry_tol; a wet/dry interface is a wall (the dry side mirrors the wet
+ * side); dry cells are not updated; after the update momenta are zeroed where
+ * h <= dry_tol and negative depths are clamped to zero (counted).
+ * Linear model (1D, ny == 1): eq. (hyp_linear) with A(x) of eq. (SWE_Aq) in
+ * wave form.
+ * `in` and `out` must not alias.  B is the bottom elevation plane.
+ * `scal` (device, may be NULL) receives the Courant number of the step.
+ */
+SWE_API swe_status swe_step(const swe_grid *grid, const swe_params *prm, const double *B,
+                    swe_fields in, swe_fields out, double dt, swe_scalars *scal,
+                    void *stream);
+
+/*
+ * adj_step - one step of length dt of the time-reversed adjoint (Sec. 4):
+ * q~(x, s) = q^(x, tf - s) solves q~_s - (A^T q~)_x = 0 in 1D and
+ * q~_s - (A1^T q~)_x - (A2^T q~)_y = 0 in 2D (Sec. 5), linearized about
+ * the sea at rest at sea_level (hbar = max(0, sea_level - B)); walls at wet/dry
+ * interfaces (zero normal velocity, Sec. 5); dry cells are not updated.
+ */
+SWE_API swe_status adj_step(const swe_grid *grid, const swe_params *prm, const double *B,
+                    swe_fields in, swe_fields out, double dt, swe_scalars *scal,
+                    void *stream);
+
+/*
+ * adj_target - the adjoint data phi = (I, 0, 0) of eqs. (phi_1d)/(phi_Alaska):
+ * I = exp(-r^2/R^2) (SWE_TARGET_GAUSS) or [r <= R] (SWE_TARGET_DISK), r the
+ * distance of the cell centre from (xc, yc) (1D: |x - xc|), and 0 in cells
+ * that are dry for the adjoint.  Writes all planes of `phi`.
+ */
+SWE_API swe_status adj_target(const swe_grid *grid, const swe_params *prm, const double *B,
+                      double xc, double yc, double R, int32_t shape, swe_fields phi,
+                      void *stream);
+
+/*
+ * swe_init - forward initial state from the initial surface eta0 (the sea
+ * floor displacement carried to the surface, Sec. 1): nonlinear
+ * h = max(0, eta0 - B), hu = hv = 0; linear eta = eta0 where wet, else 0.
+ */
+SWE_API swe_status swe_init(const swe_grid *grid, const swe_params *prm, const double *B,
+                    const double *eta0, swe_fields q, void *stream);
+
+/*
+ * swe_max_speed - device max over wet cells of the largest characteristic
+ * speed over cell size (nonlinear: max((|u|+sqrt(gh))/dx, (|v|+sqrt(gh))/dy);
+ * linear/adjoint: sqrt(g hbar)/dx and /dy), as the bit pattern of a
+ * non-negative double max-reduced into *out_bits (caller zeroes it).
+ * adjoint != 0 uses the adjoint's static coefficients.
+ */
+SWE_API swe_status swe_max_speed(const swe_grid *grid, const swe_params *prm, const double *B,
+                         swe_fields q, int32_t adjoint, uint64_t *out_bits, void *stream);
+
+/*
+ * adj_window - snapshot window of eq. (ip_timerange) (Sec. 4.2) for forward
+ * time t, with snapshots k = 0..K at reversed adjoint time s_k = k (tf-t0)/K
+ * (q^(tau = tf - s_k)).  tau ranges over [t, T], T = min(t + (tf - ts), tf);
+ * the outward-bracketing frames are
+ *   k_lo = max(0, floor((tf - T)/ds)), k_hi = min(K, ceil((tf - t)/ds)),
+ * a ratio within 1e-9 of an integer counting as that integer.  Host only, pure.
+ * Returns SWE_OK with k_lo <= k_hi, or SWE_OK with k_lo = 1, k_hi = 0 (empty)
+ * when t > tf; SWE_E_INVAL for K < 1 or tf <= t0.
+ */
+SWE_API swe_status adj_window(double t, double t0, double ts, double tf, int32_t K,
+                      int32_t *k_lo, int32_t *k_hi);
+
+/*
+ * adj_flag - flagging pass (Secs. 4.1, 4.2, and Sec. 6 for wet/dry):
+ *   m = max_{k_lo <= k <= k_hi} |(eta eta^_k + mu mu^_k) + gamma gamma^_k|
+ * (1D: |eta eta^_k + mu mu^_k|), m = 0 where the forward or the adjoint cell is
+ * dry, flag = (m > tol).  Forward eta = (h + B) - sea_level (nonlinear) or f0
+ * (linear).  frames: (K+1) snapshots of ncomp (3 in 2D, 2 in 1D) planes with
+ * the grid's pitch, snapshot k plane c at frames + (k*ncomp + c)*ny*pitch.
+ * An empty window (k_lo > k_hi) gives m = 0.  flags (int8 plane) and the
+ * optional maxip, flag_acc (|= flag), maxip_acc (= max(., m)) planes use the
+ * grid's pitch.
+ */
+SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B,
+                    swe_fields q, const double *frames, int32_t K, int32_t k_lo,
+                    int32_t k_hi, double tol, int8_t *flags, double *maxip,
+                    int8_t *flag_acc, double *maxip_acc, void *stream);
+
+/* Full problem of the two-phase driver. */
+typedef struct {
+    swe_grid grid;
+    swe_params params;      /* params.model: NONLINEAR needs ny >= 2, LINEAR ny == 1 */
+    const double *B;        /* device bottom elevation */
+    const double *eta0;     /* device initial surface */
+    double target_xc, target_yc, target_R;
+    int32_t target_shape;
+    int32_t K;              /* snapshots k = 0..K */
+    double t0, ts, tf;      /* run [t0, tf]; target time range [ts, tf] */
+    double tol;             /* flagging tolerance */
+    int32_t flag_every;     /* flag after every flag_every accepted steps (>= 1) */
+    int32_t reserved;
+    double *frames;         /* device, (K+1)*ncomp*ny*pitch doubles (output) */
+    swe_fields q_out;       /* device, final forward state (output) */
+    int8_t *flags_at;       /* device, (K+1)*ny*pitch: flags at t0 + j ds; nullable */
+    int8_t *flag_acc;       /* device plane, OR of all flags (caller zeroes); nullable */
+    double *maxip_acc;      /* device plane, max of all m (caller zeroes); nullable */
+} swe_problem;
+
+typedef struct {
+    int32_t n_adj_steps, n_sub, n_fwd_steps, n_rejected, n_flag_calls, n_clamped;
+    double dt_adj, t_end;
+} swe_result;
+
+/* Bytes of device workspace swe_run needs for this problem (0 on bad input). */
+SWE_API size_t swe_run_workspace_bytes(const swe_problem *pb);
+
+/*
+ * swe_run - the two-phase driver of Sec. 4.
+ * A. adjoint: q~(0) = phi; constant dt = ds/n_sub with ds = (tf - t0)/K,
+ *    n_sub = ceil(ds/dt_cfl), dt_cfl = cfl_desired/max(cmax/dx, cmax/dy);
+ *    snapshot k (k = 0..K) = q~ after k*n_sub steps, i.e. q^ at tf - k ds.
+ * B. forward from t0 with the state of swe_init: flag at t0; then repeat
+ *    { dt = dt0 at first, else dt*cfl_desired/cfl of the previous attempt
+ *      (unchanged if cfl = 0), clamped to the next output time t0 + j ds
+ *      (the last is tf); step; if cfl > cfl_max the step is discarded and
+ *      retried; else accept, and flag when flag_every accepted steps have
+ *      passed or an output time was reached (flags at output j stored in
+ *      flags_at[j]) } until tf.
+ * Synchronises `stream` (it reads the Courant number of each step) and
+ * returns when the run has completed.  workspace: device, at least
+ * swe_run_workspace_bytes(pb) bytes, 256-byte aligned.
+ */
+SWE_API swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_bytes,
+                   swe_result *res, void *stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+SWE_API const char *swe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWE_H */

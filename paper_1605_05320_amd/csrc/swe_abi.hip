@@ -1,0 +1,470 @@
+// C ABI entry points declared in include/swe.h: argument validation, launch
+// of the kernels, and the two-phase driver.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "swe.h"
+#include "swe_device.h"
+#include "swe_internal.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+swe_status fail(swe_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(SWE_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+int default_ly(int ny)
+{
+    // rows marched per wavefront: long enough to amortise the 2 halo rows on
+    // each side, short enough to give the chip >= 2 waves per SIMD
+    if (ny >= 4096) return 64;
+    if (ny >= 2048) return 32;
+    return 16;
+}
+
+swe_status check_grid(const swe_grid *g)
+{
+    if (!g) return fail(SWE_E_INVAL, "grid is NULL");
+    if (g->nx < 2) return fail(SWE_E_INVAL, "nx = %d < 2", g->nx);
+    if (g->ny < 1) return fail(SWE_E_INVAL, "ny = %d < 1", g->ny);
+    if (g->pitch < g->nx) return fail(SWE_E_INVAL, "pitch %d < nx %d", g->pitch, g->nx);
+    if ((long long)g->ny * g->pitch > (1LL << 40)) return fail(SWE_E_INVAL, "grid too large");
+    if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SWE_E_INVAL, "dx must be > 0");
+    if (g->ny > 1 && (!(g->dy > 0.0) || !std::isfinite(g->dy))) return fail(SWE_E_INVAL, "dy must be > 0");
+    for (int k = 0; k < 4; ++k)
+        if (g->bc[k] != SWE_BC_WALL && g->bc[k] != SWE_BC_EXTRAP)
+            return fail(SWE_E_INVAL, "bc[%d] = %d is not a boundary condition", k, g->bc[k]);
+    return SWE_OK;
+}
+
+swe_status check_params(const swe_params *p)
+{
+    if (!p) return fail(SWE_E_INVAL, "params is NULL");
+    if (p->order != 1 && p->order != 2) return fail(SWE_E_INVAL, "order must be 1 or 2");
+    if (p->transverse != 0 && p->transverse != 1) return fail(SWE_E_INVAL, "transverse must be 0 or 1");
+    if (!(p->g > 0.0)) return fail(SWE_E_INVAL, "g must be > 0");
+    if (!(p->dry_tol >= 0.0)) return fail(SWE_E_INVAL, "dry_tol must be >= 0");
+    if (!std::isfinite(p->sea_level)) return fail(SWE_E_INVAL, "sea_level must be finite");
+    if (p->model != SWE_NONLINEAR && p->model != SWE_LINEAR) return fail(SWE_E_INVAL, "unknown model");
+    return SWE_OK;
+}
+
+swe_status check_fields(const swe_grid *g, swe_fields f, const char *what)
+{
+    if (!f.f0 || !f.f1) return fail(SWE_E_INVAL, "%s: null plane", what);
+    if (g->ny > 1 && !f.f2) return fail(SWE_E_INVAL, "%s: null plane f2 in 2D", what);
+    return SWE_OK;
+}
+
+bool overlaps(const void *a, const void *b, size_t bytes)
+{
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+swe_status check_alias(const swe_grid *g, swe_fields in, swe_fields out)
+{
+    size_t bytes = (size_t)g->ny * g->pitch * sizeof(double);
+    const double *ins[3] = {in.f0, in.f1, g->ny > 1 ? in.f2 : nullptr};
+    const double *outs[3] = {out.f0, out.f1, g->ny > 1 ? out.f2 : nullptr};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (ins[a] && outs[b] && overlaps(ins[a], outs[b], bytes))
+                return fail(SWE_E_INVAL, "input plane %d overlaps output plane %d", a, b);
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (outs[a] && outs[b] && overlaps(outs[a], outs[b], bytes))
+                return fail(SWE_E_INVAL, "output planes %d and %d overlap", a, b);
+    return SWE_OK;
+}
+
+swe::KParams make_kparams(const swe_grid *g, const swe_params *p, const double *B, swe_fields in,
+                          swe_fields out, double dt, swe_scalars *sc)
+{
+    swe::KParams k;
+    std::memset(&k, 0, sizeof k);
+    k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch; k.ly = default_ly(g->ny);
+    for (int c = 0; c < 4; ++c) k.bc[c] = g->bc[c];
+    k.order = p->order; k.transverse = p->transverse;
+    k.dx = g->dx; k.dy = g->ny > 1 ? g->dy : 1.0; k.dt = dt;
+    k.g = p->g; k.sea_level = p->sea_level; k.dry_tol = p->dry_tol;
+    k.B = B;
+    k.in0 = in.f0; k.in1 = in.f1; k.in2 = in.f2;
+    k.out0 = out.f0; k.out1 = out.f1; k.out2 = out.f2;
+    if (sc) {
+        k.cfl_bits = (unsigned long long *)&sc->cfl_bits;
+        k.n_clamped = &sc->n_clamped;
+        k.n_nonfinite = &sc->n_nonfinite;
+    }
+    return k;
+}
+
+swe::CellParams make_cparams(const swe_grid *g, const swe_params *p, const double *B, swe_fields o)
+{
+    swe::CellParams c;
+    std::memset(&c, 0, sizeof c);
+    c.nx = g->nx; c.ny = g->ny; c.pitch = g->pitch;
+    c.dx = g->dx; c.dy = g->ny > 1 ? g->dy : 1.0; c.x_lo = g->x_lo; c.y_lo = g->y_lo;
+    c.g = p->g; c.sea_level = p->sea_level; c.dry_tol = p->dry_tol;
+    c.B = B;
+    c.o0 = o.f0; c.o1 = o.f1; c.o2 = g->ny > 1 ? o.f2 : nullptr;
+    return c;
+}
+
+swe_status step_common(int model, const swe_grid *grid, const swe_params *prm, const double *B,
+                       swe_fields in, swe_fields out, double dt, swe_scalars *scal, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B) return fail(SWE_E_INVAL, "B is NULL");
+    if ((st = check_fields(grid, in, "in")) != SWE_OK) return st;
+    if ((st = check_fields(grid, out, "out")) != SWE_OK) return st;
+    if ((st = check_alias(grid, in, out)) != SWE_OK) return st;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SWE_E_INVAL, "dt must be finite and > 0");
+    if (model == swe::MODEL_NL && grid->ny < 2)
+        return fail(SWE_E_INVAL, "the nonlinear model is two-dimensional (ny >= 2)");
+    if (model == swe::MODEL_LIN && grid->ny != 1)
+        return fail(SWE_E_INVAL, "the linear forward model is one-dimensional (ny == 1)");
+    swe::KParams k = make_kparams(grid, prm, B, in, out, dt, scal);
+    HIP_TRY(swe::launch_step(model, k, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *swe_last_error(void) { return g_err; }
+
+swe_status swe_step(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields in,
+                    swe_fields out, double dt, swe_scalars *scal, void *stream)
+{
+    if (!prm) return fail(SWE_E_INVAL, "params is NULL");
+    int model = prm->model == SWE_NONLINEAR ? swe::MODEL_NL : swe::MODEL_LIN;
+    return step_common(model, grid, prm, B, in, out, dt, scal, stream);
+}
+
+swe_status adj_step(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields in,
+                    swe_fields out, double dt, swe_scalars *scal, void *stream)
+{
+    return step_common(swe::MODEL_ADJ, grid, prm, B, in, out, dt, scal, stream);
+}
+
+swe_status adj_target(const swe_grid *grid, const swe_params *prm, const double *B, double xc,
+                      double yc, double R, int32_t shape, swe_fields phi, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B) return fail(SWE_E_INVAL, "B is NULL");
+    if ((st = check_fields(grid, phi, "phi")) != SWE_OK) return st;
+    if (!(R > 0.0) || !std::isfinite(R)) return fail(SWE_E_INVAL, "target radius must be > 0");
+    if (shape != SWE_TARGET_GAUSS && shape != SWE_TARGET_DISK) return fail(SWE_E_INVAL, "unknown target shape");
+    HIP_TRY(swe::launch_target(make_cparams(grid, prm, B, phi), xc, yc, R, shape, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+swe_status swe_init(const swe_grid *grid, const swe_params *prm, const double *B, const double *eta0,
+                    swe_fields q, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B || !eta0) return fail(SWE_E_INVAL, "B or eta0 is NULL");
+    if ((st = check_fields(grid, q, "q")) != SWE_OK) return st;
+    HIP_TRY(swe::launch_init(make_cparams(grid, prm, B, q), eta0, prm->model == SWE_NONLINEAR,
+                             (hipStream_t)stream));
+    return SWE_OK;
+}
+
+swe_status swe_max_speed(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                         int32_t adjoint, uint64_t *out_bits, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B || !out_bits) return fail(SWE_E_INVAL, "B or out is NULL");
+    int mode = (adjoint || prm->model == SWE_LINEAR) ? 1 : 0;
+    if (mode == 0 && (st = check_fields(grid, q, "q")) != SWE_OK) return st;
+    swe_fields none = {nullptr, nullptr, nullptr};
+    HIP_TRY(swe::launch_max_speed(make_cparams(grid, prm, B, none), q.f0, q.f1, q.f2, mode,
+                                  (unsigned long long *)out_bits, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+static double snap(double r)
+{
+    double rr = std::nearbyint(r);
+    return std::fabs(r - rr) <= 1e-9 ? rr : r;
+}
+
+swe_status adj_window(double t, double t0, double ts, double tf, int32_t K, int32_t *k_lo, int32_t *k_hi)
+{
+    if (!k_lo || !k_hi) return fail(SWE_E_INVAL, "null output");
+    if (K < 1) return fail(SWE_E_INVAL, "K must be >= 1");
+    if (!(tf > t0)) return fail(SWE_E_INVAL, "tf must exceed t0");
+    if (!std::isfinite(t) || !std::isfinite(ts)) return fail(SWE_E_INVAL, "t and ts must be finite");
+    double ds = (tf - t0) / K;
+    double T = std::fmin(t + (tf - ts), tf);
+    double sa = tf - T, sb = tf - t;
+    if (sb < 0.0) {
+        *k_lo = 1;
+        *k_hi = 0;
+        return SWE_OK;
+    }
+    double lo = std::floor(snap(sa / ds)), hi = std::ceil(snap(sb / ds));
+    if (lo < 0.0) lo = 0.0;
+    if (hi > K) hi = K;
+    *k_lo = (int32_t)lo;
+    *k_hi = (int32_t)hi;
+    return SWE_OK;
+}
+
+swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                    const double *frames, int32_t K, int32_t k_lo, int32_t k_hi, double tol,
+                    int8_t *flags, double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B || !frames) return fail(SWE_E_INVAL, "B or frames is NULL");
+    if ((st = check_fields(grid, q, "q")) != SWE_OK) return st;
+    if (K < 0) return fail(SWE_E_INVAL, "K must be >= 0");
+    if (k_lo <= k_hi && (k_lo < 0 || k_hi > K)) return fail(SWE_E_INVAL, "window [%d, %d] outside [0, %d]", k_lo, k_hi, K);
+    if (!flags && !maxip && !flag_acc && !maxip_acc) return fail(SWE_E_INVAL, "no output requested");
+    if (!std::isfinite(tol)) return fail(SWE_E_INVAL, "tol must be finite");
+    if (prm->model == SWE_NONLINEAR && grid->ny < 2) return fail(SWE_E_INVAL, "nonlinear model needs ny >= 2");
+    swe::FlagParams f;
+    std::memset(&f, 0, sizeof f);
+    f.nx = grid->nx; f.ny = grid->ny; f.pitch = grid->pitch;
+    f.twod = grid->ny > 1; f.ncomp = f.twod ? 3 : 2;
+    f.nonlinear = prm->model == SWE_NONLINEAR;
+    f.k_lo = k_lo; f.k_hi = k_hi;
+    f.sea_level = prm->sea_level; f.dry_tol = prm->dry_tol; f.tol = tol;
+    f.B = B; f.q0 = q.f0; f.q1 = q.f1; f.q2 = q.f2; f.frames = frames;
+    f.flags = flags; f.maxip = maxip; f.flag_acc = flag_acc; f.maxip_acc = maxip_acc;
+    HIP_TRY(swe::launch_flag(f, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// two-phase driver
+// ---------------------------------------------------------------------------
+struct Workspace {
+    double *a[3], *b[3];      // adjoint ping-pong is done in the frame buffer; these are the forward second set
+    int8_t *flags;
+    swe_scalars *sc;
+    unsigned long long *speed;
+    size_t bytes;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static swe_status check_problem(const swe_problem *pb)
+{
+    if (!pb) return fail(SWE_E_INVAL, "problem is NULL");
+    swe_status st;
+    if ((st = check_grid(&pb->grid)) != SWE_OK) return st;
+    if ((st = check_params(&pb->params)) != SWE_OK) return st;
+    if (!pb->B || !pb->eta0 || !pb->frames) return fail(SWE_E_INVAL, "B, eta0 or frames is NULL");
+    if ((st = check_fields(&pb->grid, pb->q_out, "q_out")) != SWE_OK) return st;
+    if (pb->K < 1) return fail(SWE_E_INVAL, "K must be >= 1");
+    if (!(pb->tf > pb->t0) || !std::isfinite(pb->tf) || !std::isfinite(pb->t0))
+        return fail(SWE_E_INVAL, "need finite t0 < tf");
+    if (!(pb->ts >= pb->t0 && pb->ts <= pb->tf)) return fail(SWE_E_INVAL, "need t0 <= ts <= tf");
+    if (pb->flag_every < 1) return fail(SWE_E_INVAL, "flag_every must be >= 1");
+    if (!(pb->target_R > 0.0)) return fail(SWE_E_INVAL, "target radius must be > 0");
+    bool twod = pb->grid.ny > 1;
+    if (twod && pb->params.model != SWE_NONLINEAR) return fail(SWE_E_INVAL, "2D runs use the nonlinear model");
+    if (!twod && pb->params.model != SWE_LINEAR) return fail(SWE_E_INVAL, "1D runs use the linear model");
+    return SWE_OK;
+}
+
+static size_t ws_layout(const swe_problem *pb, Workspace *w, char *base)
+{
+    size_t plane = (size_t)pb->grid.ny * pb->grid.pitch * sizeof(double);
+    size_t off = 0;
+    for (int c = 0; c < 3; ++c) {
+        if (w) w->a[c] = (double *)(base + off);
+        off = align256(off + plane);
+    }
+    for (int c = 0; c < 3; ++c) {
+        if (w) w->b[c] = (double *)(base + off);
+        off = align256(off + plane);
+    }
+    if (w) w->flags = (int8_t *)(base + off);
+    off = align256(off + (size_t)pb->grid.ny * pb->grid.pitch);
+    if (w) w->sc = (swe_scalars *)(base + off);
+    off = align256(off + sizeof(swe_scalars));
+    if (w) w->speed = (unsigned long long *)(base + off);
+    off = align256(off + sizeof(unsigned long long));
+    if (w) w->bytes = off;
+    return off;
+}
+
+size_t swe_run_workspace_bytes(const swe_problem *pb)
+{
+    if (check_problem(pb) != SWE_OK) return 0;
+    return ws_layout(pb, nullptr, nullptr);
+}
+
+static double bits_to_double(unsigned long long b)
+{
+    double d;
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_bytes, swe_result *res,
+                   void *stream)
+{
+    swe_status st;
+    if ((st = check_problem(pb)) != SWE_OK) return st;
+    if (!res) return fail(SWE_E_INVAL, "result is NULL");
+    if (!workspace) return fail(SWE_E_INVAL, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(SWE_E_INVAL, "workspace must be 256-byte aligned");
+    size_t need = ws_layout(pb, nullptr, nullptr);
+    if (workspace_bytes < need) return fail(SWE_E_NOMEM, "workspace %zu bytes < %zu needed", workspace_bytes, need);
+    Workspace w;
+    ws_layout(pb, &w, (char *)workspace);
+    hipStream_t s = (hipStream_t)stream;
+    std::memset(res, 0, sizeof *res);
+
+    const swe_grid *G = &pb->grid;
+    const swe_params *P = &pb->params;
+    const bool twod = G->ny > 1;
+    const int ncomp = twod ? 3 : 2;
+    const size_t plane = (size_t)G->ny * G->pitch;
+    const int K = pb->K;
+    auto frame = [&](int k) {
+        swe_fields f;
+        f.f0 = pb->frames + ((size_t)k * ncomp + 0) * plane;
+        f.f1 = pb->frames + ((size_t)k * ncomp + 1) * plane;
+        f.f2 = twod ? pb->frames + ((size_t)k * ncomp + 2) * plane : nullptr;
+        return f;
+    };
+    swe_fields A = {w.a[0], w.a[1], twod ? w.a[2] : nullptr};
+    swe_fields Bf = {w.b[0], w.b[1], twod ? w.b[2] : nullptr};
+
+    // ---- phase A: adjoint snapshots
+    HIP_TRY(hipMemsetAsync(w.speed, 0, sizeof(unsigned long long), s));
+    if ((st = swe_max_speed(G, P, pb->B, A, 1, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
+    unsigned long long spb = 0;
+    HIP_TRY(hipMemcpyAsync(&spb, w.speed, sizeof spb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // speed = max over wet cells of max(c/dx, c/dy) = max(cmax/dx, cmax/dy)
+    double smax = bits_to_double(spb);
+    double ds = (pb->tf - pb->t0) / K;
+    if (!(smax > 0.0)) return fail(SWE_E_INVAL, "no wet cell for the adjoint");
+    double dt_cfl = P->cfl_desired / smax;
+    int nsub = (int)std::ceil(ds / dt_cfl);
+    if (nsub < 1) nsub = 1;
+    double dt_adj = ds / nsub;
+    res->n_sub = nsub;
+    res->dt_adj = dt_adj;
+    if ((st = adj_target(G, P, pb->B, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape,
+                         frame(0), stream)) != SWE_OK)
+        return st;
+    for (int k = 1; k <= K; ++k) {
+        swe_fields src = frame(k - 1);
+        for (int sstep = 0; sstep < nsub; ++sstep) {
+            bool last = sstep == nsub - 1;
+            swe_fields dst = last ? frame(k) : ((sstep & 1) ? Bf : A);
+            if ((st = adj_step(G, P, pb->B, src, dst, dt_adj, nullptr, stream)) != SWE_OK) return st;
+            res->n_adj_steps++;
+            src = dst;
+        }
+    }
+
+    // ---- phase B: forward with flagging
+    swe_fields cur = A, nxt = Bf;
+    if ((st = swe_init(G, P, pb->B, pb->eta0, cur, stream)) != SWE_OK) return st;
+    double t = pb->t0;
+    auto do_flag = [&](int store_idx) -> swe_status {
+        int32_t lo, hi;
+        swe_status s2 = adj_window(t, pb->t0, pb->ts, pb->tf, K, &lo, &hi);
+        if (s2 != SWE_OK) return s2;
+        int8_t *fl = store_idx >= 0 && pb->flags_at ? pb->flags_at + (size_t)store_idx * plane : w.flags;
+        s2 = adj_flag(G, P, pb->B, cur, pb->frames, K, lo, hi, pb->tol, fl, nullptr, pb->flag_acc,
+                      pb->maxip_acc, stream);
+        res->n_flag_calls++;
+        return s2;
+    };
+    if ((st = do_flag(0)) != SWE_OK) return st;
+    HIP_TRY(hipMemsetAsync(w.speed, 0, sizeof(unsigned long long), s));
+    if ((st = swe_max_speed(G, P, pb->B, cur, 0, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
+    HIP_TRY(hipMemcpyAsync(&spb, w.speed, sizeof spb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    smax = bits_to_double(spb);
+    if (!(smax > 0.0)) return fail(SWE_E_INVAL, "no wet cell for the forward problem");
+    double dt = P->cfl_desired / smax;
+    int j = 1, since = 0, rejected = 0;
+    swe_scalars hs;
+    while (j <= K) {
+        double tout = (j == K) ? pb->tf : pb->t0 + j * ds;
+        bool fin = false;
+        if (dt >= tout - t) {
+            dt = tout - t;
+            fin = true;
+        }
+        HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(swe_scalars), s));
+        if ((st = swe_step(G, P, pb->B, cur, nxt, dt, w.sc, stream)) != SWE_OK) return st;
+        HIP_TRY(hipMemcpyAsync(&hs, w.sc, sizeof hs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        double cfl = bits_to_double(hs.cfl_bits);
+        if (hs.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state at t = %g", t);
+        if (cfl > P->cfl_max) {
+            res->n_rejected++;
+            if (++rejected > 1000) return fail(SWE_E_CFL, "no acceptable step at t = %g", t);
+            dt = dt * P->cfl_desired / cfl;
+            continue;
+        }
+        swe_fields tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        res->n_clamped += hs.n_clamped;
+        res->n_fwd_steps++;
+        t = fin ? tout : t + dt;
+        ++since;
+        if (fin) {
+            if ((st = do_flag(j)) != SWE_OK) return st;
+            since = 0;
+            ++j;
+        } else if (since == pb->flag_every) {
+            if ((st = do_flag(-1)) != SWE_OK) return st;
+            since = 0;
+        }
+        if (cfl > 0.0) dt = dt * P->cfl_desired / cfl;
+    }
+    // final state into q_out
+    size_t row_bytes = (size_t)G->nx * sizeof(double), pitch_bytes = (size_t)G->pitch * sizeof(double);
+    double *dst[3] = {pb->q_out.f0, pb->q_out.f1, pb->q_out.f2};
+    double *srcp[3] = {cur.f0, cur.f1, cur.f2};
+    for (int c = 0; c < ncomp; ++c)
+        HIP_TRY(hipMemcpy2DAsync(dst[c], pitch_bytes, srcp[c], pitch_bytes, row_bytes, G->ny,
+                                 hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    res->t_end = t;
+    return SWE_OK;
+}
+
+} // extern "C"

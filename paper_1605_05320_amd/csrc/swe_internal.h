@@ -1,0 +1,39 @@
+// Internal interface between the C ABI layer and the kernels (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swe {
+
+struct KParams;
+
+enum { MODEL_NL = 0, MODEL_LIN = 1, MODEL_ADJ = 2 };
+
+struct FlagParams {
+    int nx, ny, pitch, ncomp;
+    int twod, nonlinear;
+    int k_lo, k_hi;
+    double sea_level, dry_tol, tol;
+    const double *B, *q0, *q1, *q2, *frames;
+    int8_t *flags;
+    double *maxip;
+    int8_t *flag_acc;
+    double *maxip_acc;
+};
+
+struct CellParams {
+    int nx, ny, pitch;
+    double dx, dy, x_lo, y_lo;
+    double g, sea_level, dry_tol;
+    const double *B;
+    double *o0, *o1, *o2;
+};
+
+hipError_t launch_step(int model, const KParams &P, hipStream_t s);
+hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_target(const CellParams &C, double xc, double yc, double R, int shape, hipStream_t s);
+hipError_t launch_init(const CellParams &C, const double *eta0, int nonlinear, hipStream_t s);
+hipError_t launch_max_speed(const CellParams &C, const double *q0, const double *q1, const double *q2,
+                            int mode, unsigned long long *out, hipStream_t s);
+
+} // namespace swe

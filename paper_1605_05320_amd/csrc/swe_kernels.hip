@@ -1,0 +1,425 @@
+// HIP kernels for gfx950: the marching finite-volume step (2D and 1D),
+// the flagging pass and the small per-cell helpers (target data, initial
+// state, max characteristic speed).
+//
+// Marching step.  One wavefront owns a strip of 64 columns (60 output
+// columns plus a 2-column halo on each side; lane l holds column
+// i = 60*strip + l - 2) and marches down `ly` rows.  Everything a row needs
+// from the rows above and below is carried in registers (cells of rows
+// r..r+2, y-edges r-1/2, r+1/2, r+3/2, x-edges of rows r and r+1, the
+// correction flux G of edge r-1/2), and everything it needs from the
+// columns left and right comes from neighbouring lanes by cross-lane
+// shuffles.  So each edge of a strip is solved exactly once, the state is
+// read once per strip (plus 4 halo rows per chunk and 4 halo columns per
+// strip) and written once, there is no LDS footprint and no barrier.
+#include "swe_device.h"
+#include "swe_internal.h"
+
+namespace swe {
+
+// Per-row correction flux of a y-edge with its transverse terms.
+template <class M>
+__device__ __forceinline__ void g_tilde(const Edge &e, const Edge &lo, const Edge &hi, const KParams &P,
+                                        double nuy, double hnux,
+                                        const double *t0, int ty0, const double *t1, int ty1,
+                                        const double *t2, int ty2, const double *t3, int ty3,
+                                        double G[3])
+{
+    G[0] = 0.0; G[1] = 0.0; G[2] = 0.0;
+    if (e.type != E_WET) return;
+    double Gn[3] = {0.0, 0.0, 0.0};
+    if (P.order == 2) {
+        double cx[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int p = 0; p < M::NW; ++p) {
+            const bool from_lo = e.s[p] > 0.0;
+            double uz[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) uz[c] = from_lo ? lo.z[p][c] : hi.z[p][c];
+            double dd, du;
+            if (M::zc(p, 0) && M::zc(p, 1)) {
+                dd = e.z[p][0] * e.z[p][0] + e.z[p][1] * e.z[p][1];
+                du = uz[0] * e.z[p][0] + uz[1] * e.z[p][1];
+                if (M::zc(p, 2)) {
+                    dd = dd + e.z[p][2] * e.z[p][2];
+                    du = du + uz[2] * e.z[p][2];
+                }
+            } else {
+                dd = e.z[p][2] * e.z[p][2];
+                du = uz[2] * e.z[p][2];
+            }
+            if (dd == 0.0) continue;
+            double phi = mc_phi(du / dd);
+            double as = fabs(e.s[p]);
+            double a = 1.0 - nuy * as;
+            double w;
+            if (M::FWAVE)
+                w = e.s[p] > 0.0 ? a : (e.s[p] < 0.0 ? -a : 0.0);
+            else
+                w = as * a;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (M::zc(p, c)) cx[c] = cx[c] + w * (phi * e.z[p][c]);
+        }
+        Gn[0] = 0.5 * cx[0]; Gn[1] = 0.5 * cx[1]; Gn[2] = 0.5 * cx[2];
+    }
+    to_phys(true, Gn, G);
+    if (P.transverse)
+        transverse_gather<M>(e, true, hnux, t0, ty0 == E_WET, t1, ty1 == E_WET, t2, ty2 == E_WET,
+                             t3, ty3 == E_WET, G);
+}
+
+template <class M>
+__global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
+{
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * STRIP + lane - HALO;
+    const int j0 = blockIdx.y * P.ly;
+    const int j1 = min(j0 + P.ly, P.ny);
+    const double nux = P.dt / P.dx, nuy = P.dt / P.dy;
+    const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
+    const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
+    const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
+    const int up = lane > 0 ? lane - 1 : 0;
+    const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
+    double cfl = 0.0;
+    int nclamp = 0, nbad = 0;
+
+    using Cell = typename M::Cell;
+    Cell cA = M::load(P, i, j0 - 2);
+    Cell cB = M::load(P, i, j0 - 1);
+    Cell cC = M::load(P, i, j0);
+    Cell cD = M::load(P, i, j0 + 1);
+
+    Edge yS, yN, xCur;
+    double G_S[3];
+    double xCurE_am[3];
+    int xCurE_t;
+    {
+        Edge yS2, xPrev;
+        M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
+        M::solve(cB, cC, true, P, yS);             // y-edge j0 - 1/2
+        M::solve(cC, cD, true, P, yN);             // y-edge j0 + 1/2
+        Cell lB = M::shfl_cell(cB, up);
+        M::solve(lB, cB, false, P, xPrev);         // x-edge (i - 1/2, j0 - 1)
+        Cell lC = M::shfl_cell(cC, up);
+        M::solve(lC, cC, false, P, xCur);          // x-edge (i - 1/2, j0)
+        double xPrevE_am[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xPrevE_am[c] = shfl(xPrev.am[c], dn);
+            xCurE_am[c] = shfl(xCur.am[c], dn);
+        }
+        int xPrevE_t = shfl(xPrev.type, dn);
+        xCurE_t = shfl(xCur.type, dn);
+        g_tilde<M>(yS, yS2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, xPrevE_am, xPrevE_t,
+                   xCur.ap, xCur.type, xCurE_am, xCurE_t, G_S);
+        if (core && j0 < P.ny) {
+#pragma unroll
+            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yS.s[p]));
+        }
+    }
+
+    for (int r = j0; r < j1; ++r) {
+        Cell cE = M::load(P, i, r + 2);
+        Edge yNN, xNext;
+        M::solve(cD, cE, true, P, yNN);            // y-edge r + 3/2
+        Cell lD = M::shfl_cell(cD, up);
+        M::solve(lD, cD, false, P, xNext);         // x-edge (i - 1/2, r + 1)
+        double xNextE_am[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xNextE_am[c] = shfl(xNext.am[c], dn);
+        int xNextE_t = shfl(xNext.type, dn);
+
+        // G(i, r + 1/2)
+        double G_N[3];
+        g_tilde<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE_am, xCurE_t,
+                   xNext.ap, xNext.type, xNextE_am, xNextE_t, G_N);
+
+        // F(i - 1/2, r): limiter from lanes -1/+1, transverse from the y-edges
+        // of columns i-1 (lane - 1) and i (own).
+        double F_W[3] = {0.0, 0.0, 0.0};
+        {
+            double Fn[3] = {0.0, 0.0, 0.0};
+            if (P.order == 2) correction_lanes<M>(xCur, nux, lane, Fn);
+            double yS_ap_W[3], yN_am_W[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                yS_ap_W[c] = shfl(yS.ap[c], up);
+                yN_am_W[c] = shfl(yN.am[c], up);
+            }
+            int yS_t_W = shfl(yS.type, up), yN_t_W = shfl(yN.type, up);
+            if (xCur.type == E_WET) {
+                to_phys(false, Fn, F_W);
+                if (P.transverse)
+                    transverse_gather<M>(xCur, false, hnuy, yS_ap_W, yS_t_W == E_WET, yN_am_W,
+                                         yN_t_W == E_WET, yS.ap, yS.type == E_WET, yN.am,
+                                         yN.type == E_WET, F_W);
+            }
+        }
+        double F_E[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) F_E[c] = shfl(F_W[c], dn);
+
+        if (core) {
+            double o[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                double qv = M::q(cC, c);
+                if (M::updates(cC)) {
+                    qv = qv - nux * (xCur.ap[c] + xCurE_am[c]);
+                    qv = qv - nuy * (yS.ap[c] + yN.am[c]);
+                    qv = qv - nux * (F_E[c] - F_W[c]);
+                    qv = qv - nuy * (G_N[c] - G_S[c]);
+                }
+                o[c] = qv;
+            }
+            if (M::DRYFIX) {
+                // nonlinear dry-cell fix
+                if (!(o[0] > P.dry_tol)) { o[1] = 0.0; o[2] = 0.0; }
+                if (o[0] < 0.0) { o[0] = 0.0; ++nclamp; }
+            }
+            if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) ++nbad;
+            size_t k = (size_t)r * P.pitch + i;
+            P.out0[k] = o[0];
+            P.out1[k] = o[1];
+            P.out2[k] = o[2];
+        }
+        if (xedge_in)
+#pragma unroll
+            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nux * fabs(xCur.s[p]));
+        if (core)
+#pragma unroll
+            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yN.s[p]));
+
+        // roll the window down one row
+        yS = yN;
+        yN = yNN;
+        xCur = xNext;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { xCurE_am[c] = xNextE_am[c]; G_S[c] = G_N[c]; }
+        xCurE_t = xNextE_t;
+        cC = cD;
+        cD = cE;
+    }
+
+    cfl = wave_max(cfl);
+    if (lane == 0 && P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+    unsigned long long mc = __ballot(nclamp > 0), mb = __ballot(nbad > 0);
+    if (lane == 0) {
+        if (mc && P.n_clamped) atomicAdd(P.n_clamped, __popcll(mc));
+        if (mb && P.n_nonfinite) atomicAdd(P.n_nonfinite, __popcll(mb));
+    }
+}
+
+// One row (ny == 1): the x-sweep of the marching step without y-terms.
+template <class M>
+__global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
+{
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * STRIP + lane - HALO;
+    const double nu = P.dt / P.dx;
+    const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
+    const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
+    const int up = lane > 0 ? lane - 1 : 0;
+    const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
+    using Cell = typename M::Cell;
+    Cell c = M::load(P, i, 0);
+    Cell l = M::shfl_cell(c, up);
+    Edge x;
+    M::solve(l, c, false, P, x);
+    double F[3] = {0.0, 0.0, 0.0};
+    if (P.order == 2) {
+        double Fn[3] = {0.0, 0.0, 0.0};
+        correction_lanes<M>(x, nu, lane, Fn);
+        if (x.type == E_WET) to_phys(false, Fn, F);
+    }
+    double FE[3], amE[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { FE[k] = shfl(F[k], dn); amE[k] = shfl(x.am[k], dn); }
+    if (core) {
+        double o[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            double qv = M::q(c, k);
+            if (M::updates(c)) {
+                qv = qv - nu * (x.ap[k] + amE[k]);
+                qv = qv - nu * (FE[k] - F[k]);
+            }
+            o[k] = qv;
+        }
+        P.out0[i] = o[0];
+        P.out1[i] = o[1];
+    }
+    double cfl = 0.0;
+    if (xedge_in)
+#pragma unroll
+        for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nu * fabs(x.s[p]));
+    cfl = wave_max(cfl);
+    if (lane == 0 && P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+}
+
+// ---------------------------------------------------------------------------
+// Flagging pass: one thread per cell, coalesced across the row.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_flag(FlagParams F)
+{
+    const long long n = (long long)F.nx * F.ny;
+    const size_t plane = (size_t)F.ny * F.pitch;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
+        size_t k = (size_t)j * F.pitch + i;
+        double B = F.B[k];
+        double hb = dmax(0.0, F.sea_level - B);
+        bool adj_wet = hb > F.dry_tol;
+        double q0 = F.q0[k];
+        bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
+        double m = 0.0;
+        if (adj_wet && fwd_wet) {
+            double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
+            double q1 = F.q1[k];
+            double q2 = F.twod ? F.q2[k] : 0.0;
+            const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
+            for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
+                double ip = eta * fr[0] + q1 * fr[plane];
+                if (F.twod) ip = ip + q2 * fr[2 * plane];
+                m = dmax(m, fabs(ip));
+            }
+        }
+        int8_t fl = m > F.tol ? 1 : 0;
+        if (F.flags) F.flags[k] = fl;
+        if (F.maxip) F.maxip[k] = m;
+        if (F.flag_acc) F.flag_acc[k] = (int8_t)(F.flag_acc[k] | fl);
+        if (F.maxip_acc) F.maxip_acc[k] = dmax(F.maxip_acc[k], m);
+    }
+}
+
+// Target data, initial state, maximum speed: per-cell helpers.
+__global__ void __launch_bounds__(256) k_target(CellParams C, double xc, double yc, double R, int shape)
+{
+    const long long n = (long long)C.nx * C.ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / C.nx), i = (int)(idx - (long long)j * C.nx);
+        size_t k = (size_t)j * C.pitch + i;
+        double x = C.x_lo + (i + 0.5) * C.dx;
+        double ddx = x - xc;
+        double r2 = ddx * ddx;
+        if (C.ny > 1) {
+            double y = C.y_lo + (j + 0.5) * C.dy;
+            double ddy = y - yc;
+            r2 = r2 + ddy * ddy;
+        }
+        double v = shape == 0 ? exp(-r2 / (R * R)) : (r2 <= R * R ? 1.0 : 0.0);
+        double hb = dmax(0.0, C.sea_level - C.B[k]);
+        C.o0[k] = hb > C.dry_tol ? v : 0.0;
+        C.o1[k] = 0.0;
+        if (C.o2) C.o2[k] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_init(CellParams C, const double *eta0, int nonlinear)
+{
+    const long long n = (long long)C.nx * C.ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / C.nx), i = (int)(idx - (long long)j * C.nx);
+        size_t k = (size_t)j * C.pitch + i;
+        double B = C.B[k];
+        if (nonlinear) {
+            C.o0[k] = dmax(0.0, eta0[k] - B);
+        } else {
+            double hb = dmax(0.0, C.sea_level - B);
+            C.o0[k] = hb > C.dry_tol ? eta0[k] : 0.0;
+        }
+        C.o1[k] = 0.0;
+        if (C.o2) C.o2[k] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_max_speed(CellParams C, const double *q0, const double *q1,
+                                                   const double *q2, int mode, unsigned long long *out)
+{
+    // mode 0: nonlinear state; 1: static linear coefficients
+    const long long n = (long long)C.nx * C.ny;
+    double m = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / C.nx), i = (int)(idx - (long long)j * C.nx);
+        size_t k = (size_t)j * C.pitch + i;
+        double a, b;
+        if (mode == 0) {
+            double h = q0[k];
+            if (!(h > C.dry_tol)) continue;
+            double c = sqrt(C.g * h);
+            a = (fabs(q1[k] / h) + c) / C.dx;
+            b = C.ny > 1 ? (fabs(q2[k] / h) + c) / C.dy : 0.0;
+        } else {
+            double hb = dmax(0.0, C.sea_level - C.B[k]);
+            if (!(hb > C.dry_tol)) continue;
+            double c = sqrt(C.g * hb);
+            a = c / C.dx;
+            b = C.ny > 1 ? c / C.dy : 0.0;
+        }
+        m = dmax(m, dmax(a, b));
+    }
+    m = wave_max(m);
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int grid_cells(long long n)
+{
+    long long b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_step(int model, const KParams &P, hipStream_t s)
+{
+    dim3 block(WAVE);
+    if (P.ny == 1) {
+        dim3 grid((P.nx + STRIP - 1) / STRIP);
+        if (model == MODEL_ADJ) hipLaunchKernelGGL(k_step1d<ADJ<false>>, grid, block, 0, s, P);
+        else if (model == MODEL_LIN) hipLaunchKernelGGL(k_step1d<LIN1>, grid, block, 0, s, P);
+        else return hipErrorInvalidValue;
+    } else {
+        dim3 grid((P.nx + STRIP - 1) / STRIP, (P.ny + P.ly - 1) / P.ly);
+        if (model == MODEL_NL) hipLaunchKernelGGL(k_march2d<NL>, grid, block, 0, s, P);
+        else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, P);
+        else return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flag(const FlagParams &F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flag, dim3(grid_cells((long long)F.nx * F.ny)), dim3(256), 0, s, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_target(const CellParams &C, double xc, double yc, double R, int shape, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_target, dim3(grid_cells((long long)C.nx * C.ny)), dim3(256), 0, s, C, xc, yc, R, shape);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const CellParams &C, const double *eta0, int nonlinear, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init, dim3(grid_cells((long long)C.nx * C.ny)), dim3(256), 0, s, C, eta0, nonlinear);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_speed(const CellParams &C, const double *q0, const double *q1, const double *q2,
+                            int mode, unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_max_speed, dim3(grid_cells((long long)C.nx * C.ny)), dim3(256), 0, s, C, q0, q1,
+                       q2, mode, out);
+    return hipGetLastError();
+}
+
+} // namespace swe

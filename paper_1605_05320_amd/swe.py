@@ -1,0 +1,209 @@
+"""Thin ctypes binding of ``libswe.so`` (the C ABI of ``include/swe.h``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Device memory and streams come from PyTorch
+(float64 CUDA/HIP tensors; a 2D field is an (ny, nx) tensor whose row stride
+is the grid pitch).  If the library is missing the import of a function
+raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswe.so")
+
+OK, E_INVAL, E_CFL, E_HIP, E_NOMEM, E_NONFINITE, E_NEGDEPTH = 0, -1, -2, -3, -4, -5, -6
+BC_WALL, BC_EXTRAP = 0, 1
+NONLINEAR, LINEAR = 0, 1
+GAUSS, DISK = 0, 1
+
+
+class SweError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"swe status {status}: {msg}")
+        self.status = status
+
+
+class swe_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("pitch", C.c_int32), ("bc", C.c_int32 * 4),
+                ("dx", C.c_double), ("dy", C.c_double), ("x_lo", C.c_double), ("y_lo", C.c_double)]
+
+
+class swe_params(C.Structure):
+    _fields_ = [("model", C.c_int32), ("order", C.c_int32), ("transverse", C.c_int32),
+                ("reserved", C.c_int32), ("g", C.c_double), ("sea_level", C.c_double),
+                ("dry_tol", C.c_double), ("cfl_desired", C.c_double), ("cfl_max", C.c_double)]
+
+
+class swe_fields(C.Structure):
+    _fields_ = [("f0", C.c_void_p), ("f1", C.c_void_p), ("f2", C.c_void_p)]
+
+
+class swe_problem(C.Structure):
+    _fields_ = [("grid", swe_grid), ("params", swe_params), ("B", C.c_void_p), ("eta0", C.c_void_p),
+                ("target_xc", C.c_double), ("target_yc", C.c_double), ("target_R", C.c_double),
+                ("target_shape", C.c_int32), ("K", C.c_int32),
+                ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
+                ("flag_every", C.c_int32), ("reserved", C.c_int32),
+                ("frames", C.c_void_p), ("q_out", swe_fields), ("flags_at", C.c_void_p),
+                ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p)]
+
+
+class swe_result(C.Structure):
+    _fields_ = [("n_adj_steps", C.c_int32), ("n_sub", C.c_int32), ("n_fwd_steps", C.c_int32),
+                ("n_rejected", C.c_int32), ("n_flag_calls", C.c_int32), ("n_clamped", C.c_int32),
+                ("dt_adj", C.c_double), ("t_end", C.c_double)]
+
+
+SCALARS_BYTES = 16  # swe_scalars: uint64 cfl_bits, int32 n_clamped, int32 n_nonfinite
+
+_lib = None
+
+
+def lib():
+    """Load libswe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                              "(python -m paper_1605_05320_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
+                     "adj_flag", "swe_run"):
+            getattr(L, name).restype = C.c_int
+        L.swe_run_workspace_bytes.restype = C.c_size_t
+        L.swe_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != OK:
+        raise SweError(st, lib().swe_last_error().decode())
+
+
+@dataclass
+class Grid:
+    nx: int
+    ny: int
+    dx: float
+    dy: float = 1.0
+    x_lo: float = 0.0
+    y_lo: float = 0.0
+    bc: tuple = (BC_WALL, BC_WALL, BC_WALL, BC_WALL)
+    pitch: int | None = None
+
+    def c(self) -> swe_grid:
+        g = swe_grid(self.nx, self.ny, self.pitch or self.nx)
+        for k in range(4):
+            g.bc[k] = self.bc[k]
+        g.dx, g.dy, g.x_lo, g.y_lo = self.dx, self.dy, self.x_lo, self.y_lo
+        return g
+
+
+@dataclass
+class Params:
+    model: int = NONLINEAR
+    order: int = 2
+    transverse: int = 1
+    g: float = 9.81
+    sea_level: float = 0.0
+    dry_tol: float = 1.0e-3
+    cfl_desired: float = 0.9
+    cfl_max: float = 1.0
+
+    def c(self) -> swe_params:
+        return swe_params(self.model, self.order, self.transverse, 0, self.g, self.sea_level,
+                          self.dry_tol, self.cfl_desired, self.cfl_max)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def fields(q) -> swe_fields:
+    q = list(q) + [None] * (3 - len(q))
+    return swe_fields(*(None if t is None else t.data_ptr() for t in q[:3]))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def swe_step(grid: Grid, prm: Params, B, q_in, q_out, dt: float, scal=None, stream=None):
+    _check(lib().swe_step(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q_in), fields(q_out),
+                          C.c_double(dt), _ptr(scal), _stream(stream)))
+
+
+def adj_step(grid: Grid, prm: Params, B, q_in, q_out, dt: float, scal=None, stream=None):
+    _check(lib().adj_step(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q_in), fields(q_out),
+                          C.c_double(dt), _ptr(scal), _stream(stream)))
+
+
+def adj_target(grid: Grid, prm: Params, B, xc, yc, R, shape, phi, stream=None):
+    _check(lib().adj_target(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), C.c_double(xc),
+                            C.c_double(yc), C.c_double(R), C.c_int32(shape), fields(phi),
+                            _stream(stream)))
+
+
+def swe_init(grid: Grid, prm: Params, B, eta0, q, stream=None):
+    _check(lib().swe_init(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), _ptr(eta0), fields(q),
+                          _stream(stream)))
+
+
+def swe_max_speed(grid: Grid, prm: Params, B, q, adjoint: int, out_bits, stream=None):
+    _check(lib().swe_max_speed(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q or []),
+                               C.c_int32(adjoint), _ptr(out_bits), _stream(stream)))
+
+
+def adj_window(t, t0, ts, tf, K):
+    lo, hi = C.c_int32(), C.c_int32()
+    _check(lib().adj_window(C.c_double(t), C.c_double(t0), C.c_double(ts), C.c_double(tf),
+                            C.c_int32(K), C.byref(lo), C.byref(hi)))
+    return lo.value, hi.value
+
+
+def adj_flag(grid: Grid, prm: Params, B, q, frames, K, k_lo, k_hi, tol, flags=None, maxip=None,
+             flag_acc=None, maxip_acc=None, stream=None):
+    _check(lib().adj_flag(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), _ptr(frames),
+                          C.c_int32(K), C.c_int32(k_lo), C.c_int32(k_hi), C.c_double(tol),
+                          _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc), _stream(stream)))
+
+
+def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, frames, q_out,
+                 flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS) -> swe_problem:
+    pb = swe_problem()
+    pb.grid = grid.c()
+    pb.params = prm.c()
+    pb.B, pb.eta0 = B.data_ptr(), eta0.data_ptr()
+    pb.target_xc, pb.target_yc, pb.target_R = target
+    pb.target_shape = shape
+    pb.K = K
+    pb.t0, pb.ts, pb.tf, pb.tol = t0, ts, tf, tol
+    pb.flag_every = flag_every
+    pb.frames = frames.data_ptr()
+    pb.q_out = fields(q_out)
+    pb.flags_at = None if flags_at is None else flags_at.data_ptr()
+    pb.flag_acc = None if flag_acc is None else flag_acc.data_ptr()
+    pb.maxip_acc = None if maxip_acc is None else maxip_acc.data_ptr()
+    # the problem holds raw device pointers: keep the tensors alive with it
+    pb._keep = (B, eta0, frames, tuple(q_out), flags_at, flag_acc, maxip_acc)
+    return pb
+
+
+def swe_run_workspace_bytes(pb: swe_problem) -> int:
+    return lib().swe_run_workspace_bytes(C.byref(pb))
+
+
+def swe_run(pb: swe_problem, workspace, stream=None) -> swe_result:
+    res = swe_result()
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().swe_run(C.byref(pb), _ptr(workspace), C.c_size_t(nbytes), C.byref(res),
+                         _stream(stream)))
+    return res

@@ -1,0 +1,346 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Same seeded inputs on both sides; fields are compared element by element.
+The bar: |f_gpu - f_oracle| <= 1e-12 * max|f_oracle| per field (eta = h + B
+for the depth, so that the 4000 m of water do not hide errors), flags
+identical except cells whose max inner product lies within 1e-12 relative of
+the tolerance.  Both sides evaluate the same operations in the same order
+without FMA contraction, so in practice the results are bit-identical; the
+tests also report that.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1605_05320_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+REL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_05320_amd import swe
+    swe.lib()
+    return swe
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def close(a, b, scale=None):
+    a, b = np.asarray(a), np.asarray(b)
+    scale = np.abs(b).max() if scale is None else scale
+    return np.abs(a - b).max() <= REL * max(scale, 1e-300)
+
+
+def pair_grids(O, S, nx, ny, dx, dy, bc=(0, 0, 0, 0), x_lo=0.0, y_lo=0.0, pitch=None):
+    return (O.Grid(nx, ny, dx, dy, x_lo, y_lo, bc),
+            S.Grid(nx, ny, dx, dy, x_lo, y_lo, bc, pitch))
+
+
+def nl_steps_gpu(S, g, p, B, q, dts):
+    Bd = dev(B)
+    a = [dev(x) for x in q]
+    b = [torch.empty_like(x) for x in a]
+    sc = torch.zeros(2, dtype=torch.int64, device=DEV)
+    cfls = []
+    for dt in dts:
+        sc.zero_()
+        S.swe_step(g, p, Bd, a, b, dt, sc)
+        a, b = b, a
+        cfls.append(float(sc[0:1].view(torch.float64).item()))
+    torch.cuda.synchronize()
+    return [host(x) for x in a], cfls, int(sc[1].item() & 0xffffffff)
+
+
+def nl_steps_cpu(O, g, p, B, q, dts):
+    h, hu, hv = q
+    cfls = []
+    for dt in dts:
+        h, hu, hv, cfl, _ = O.swe_step(g, p, B, h, hu, hv, dt)
+        cfls.append(cfl)
+    return [h, hu, hv], cfls
+
+
+def compare_nl(B, g_, c_):
+    eta_g, eta_c = g_[0] + B, c_[0] + B
+    ok = close(eta_g, eta_c, np.abs(eta_c).max() + 1.0) and close(g_[1], c_[1]) and close(g_[2], c_[2])
+    exact = all(np.array_equal(x, y) for x, y in zip(g_, c_))
+    return ok, exact
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,ny,seed,order,trans", [
+    (200, 150, 2, 2, 1),       # several strips and chunks, ragged tails in x and y
+    (130, 97, 12, 2, 1),
+    (64, 64, 22, 1, 1),
+    (61, 35, 3, 2, 0),         # one strip + 1 column, no transverse terms
+])
+def test_nl_step_parity(oracle, S, n, ny, seed, order, trans):
+    O = oracle
+    b = I.basin(n, seed, ny=ny)
+    go, gs = pair_grids(O, S, n, ny, b.grid.dx, b.grid.dy)
+    po = O.Params(order=order, transverse=trans)
+    ps = S.Params(order=order, transverse=trans)
+    q = O.init_state(go, po, O.NONLINEAR, b.B, b.eta0 * 20.0)
+    dt = O.dt0(go, po, O.NONLINEAR, b.B, *q)
+    dts = [dt * f for f in (1.0, 0.9, 0.95, 0.7, 1.0, 0.85, 0.9, 0.9, 0.9, 0.9)]
+    qg, cg, ncl = nl_steps_gpu(S, gs, ps, b.B, q, dts)
+    qc, cc = nl_steps_cpu(O, go, po, b.B, q, dts)
+    ok, exact = compare_nl(b.B, qg, qc)
+    print(f"nl n={n}x{ny} order={order} trans={trans}: bit-exact={exact}")
+    assert ok
+    assert np.allclose(cg, cc, rtol=REL, atol=0)
+    assert ncl == 0
+
+
+def test_nl_lake_at_rest_gpu_bit_exact(oracle, S):
+    O = oracle
+    b = I.basin(256, 2)
+    go, gs = pair_grids(O, S, 256, 256, b.grid.dx, b.grid.dy)
+    q = O.init_state(go, O.Params(), O.NONLINEAR, b.B, np.zeros_like(b.B))
+    dt = O.dt0(go, O.Params(), O.NONLINEAR, b.B, *q)
+    qg, _, _ = nl_steps_gpu(S, gs, S.Params(), b.B, q, [dt] * 50)
+    assert np.array_equal(qg[0], q[0])
+    assert not qg[1].any() and not qg[2].any()
+
+
+def test_nl_extrap_pitch_and_small_grids(oracle, S):
+    O = oracle
+    rng = np.random.default_rng(5)
+    for (nx, ny, bc) in [(2, 2, (0, 0, 0, 0)), (3, 5, (1, 1, 1, 1)), (70, 3, (0, 1, 1, 0)), (7, 130, (1, 0, 0, 1))]:
+        B = -rng.uniform(5.0, 60.0, (ny, nx))
+        B[0, -1] = 1.0                                     # a dry cell
+        h = np.maximum(0.0, 0.3 * rng.standard_normal((ny, nx)) - B)
+        hu, hv = rng.standard_normal((ny, nx)) * 2, rng.standard_normal((ny, nx)) * 2
+        hu[h <= 1e-3] = 0.0
+        hv[h <= 1e-3] = 0.0
+        go, gs = pair_grids(O, S, nx, ny, 50.0, 70.0, bc)
+        p = O.Params()
+        dts = [0.5, 0.4, 0.45]
+        qc, cc = nl_steps_cpu(O, go, p, B, [h, hu, hv], dts)
+        # pitch > nx: embed in wider rows
+        pitch = nx + 5
+        gs.pitch = pitch
+        def wide(a):
+            w = np.full((ny, pitch), np.nan)
+            w[:, :nx] = a
+            return w
+        qg, cg, _ = nl_steps_gpu(S, gs, S.Params(), wide(B), [wide(h), wide(hu), wide(hv)], dts)
+        qg = [x[:, :nx] for x in qg]
+        ok, exact = compare_nl(B, qg, qc)
+        assert ok, (nx, ny, bc)
+        assert np.allclose(cg, cc, rtol=REL, atol=0)
+
+
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,ny,seed", [(150, 110, 3), (64, 61, 7)])
+def test_adj_step_parity_2d(oracle, S, n, ny, seed):
+    O = oracle
+    b = I.basin(n, seed, ny=ny)
+    go, gs = pair_grids(O, S, n, ny, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    xc, yc, _ = b.target
+    phi = O.target(go, p, b.B, xc, yc, 80e3, O.GAUSS)
+    rng = np.random.default_rng(seed)
+    q = [phi, 0.01 * rng.standard_normal(phi.shape), 0.01 * rng.standard_normal(phi.shape)]
+    ns, dt = O.adj_nsub(go, p, b.B, 0.0, 3600.0, 4)
+    qc = list(q)
+    for _ in range(8):
+        qc = list(O.adj_step(go, p, b.B, *qc, dt)[:3])
+    Bd = dev(b.B)
+    a = [dev(x) for x in q]
+    bb = [torch.empty_like(x) for x in a]
+    for _ in range(8):
+        S.adj_step(gs, S.Params(), Bd, a, bb, dt)
+        a, bb = bb, a
+    qg = [host(x) for x in a]
+    exact = all(np.array_equal(x, y) for x, y in zip(qg, qc))
+    print(f"adj 2d {n}x{ny}: bit-exact={exact}")
+    for x, y in zip(qg, qc):
+        assert close(x, y)
+
+
+@pytest.mark.parametrize("n,order", [(2000, 2), (333, 2), (61, 1)])
+def test_1d_parity(oracle, S, n, order):
+    O = oracle
+    s = I.shelf1d(n, seed=4)
+    go, gs = pair_grids(O, S, n, 1, s.dx, 1.0, x_lo=s.x_lo)
+    po = O.Params(order=order)
+    ps = S.Params(model=S.LINEAR, order=order)
+    dt = 0.9 * s.dx / math.sqrt(9.81 * 4000.0)
+    e, m = s.eta0.copy(), np.zeros(n)
+    Bd = dev(s.B)
+    a = [dev(e), dev(m)]
+    b = [torch.empty_like(x) for x in a]
+    for _ in range(25):
+        e, m, _ = O.lin_step(go, po, s.B, e, m, dt)
+        S.swe_step(gs, ps, Bd, a, b, dt)
+        a, b = b, a
+    assert close(host(a[0]), e) and close(host(a[1]), m)
+    # adjoint
+    phi = O.target(go, po, s.B, *s.target, O.GAUSS).ravel()
+    ae, am = phi.copy(), np.zeros(n)
+    a = [dev(ae), dev(am)]
+    b = [torch.empty_like(x) for x in a]
+    for _ in range(25):
+        ae, am, _, _ = O.adj_step(go, po, s.B, ae, am, None, dt)
+        ae, am = ae.ravel(), am.ravel()
+        S.adj_step(gs, ps, Bd, a, b, dt)
+        a, b = b, a
+    assert close(host(a[0]), ae) and close(host(a[1]), am)
+
+
+# --------------------------------------------------------------------------
+def test_target_and_init_parity(oracle, S):
+    O = oracle
+    b = I.basin(97, 3)
+    go, gs = pair_grids(O, S, 97, 97, b.grid.dx, b.grid.dy)
+    xc, yc, R = b.target
+    Bd = dev(b.B)
+    for shape in (O.GAUSS, O.DISK):
+        phi_c = O.target(go, O.Params(), b.B, xc, yc, 60e3, shape)
+        out = [torch.empty(97, 97, dtype=torch.float64, device=DEV) for _ in range(3)]
+        S.adj_target(gs, S.Params(), Bd, xc, yc, 60e3, shape, out)
+        assert close(host(out[0]), phi_c)
+        assert not host(out[1]).any() and not host(out[2]).any()
+    q_c = O.init_state(go, O.Params(), O.NONLINEAR, b.B, b.eta0)
+    S.swe_init(gs, S.Params(), Bd, dev(b.eta0), out)
+    for x, y in zip(out, q_c):
+        assert np.array_equal(host(x), y)
+
+
+@pytest.mark.parametrize("twod", [True, False])
+def test_flag_parity_bit_exact(oracle, S, twod):
+    O = oracle
+    rng = np.random.default_rng(11)
+    nx, ny, K = (131, 77, 9) if twod else (500, 1, 6)
+    ncomp = 3 if twod else 2
+    B = -rng.uniform(-20.0, 300.0, (ny, nx))
+    q0 = np.maximum(0.0, rng.normal(0, 0.3, (ny, nx)) - B) if twod else rng.normal(0, 0.1, (ny, nx))
+    q1, q2 = rng.normal(0, 1, (ny, nx)), rng.normal(0, 1, (ny, nx))
+    frames = rng.normal(0, 1e-3, (K + 1, ncomp, ny, nx))
+    go, gs = pair_grids(O, S, nx, ny, 100.0, 100.0)
+    model = O.NONLINEAR if twod else O.LINEAR
+    tol = 2e-3
+    po, ps = O.Params(), S.Params(model=model)
+    Bd, fd = dev(B), dev(frames)
+    qd = [dev(q0), dev(q1), dev(q2)] if twod else [dev(q0), dev(q1)]
+    acc_c = np.zeros((ny, nx), np.int8)
+    macc_c = np.zeros((ny, nx))
+    acc_g = torch.zeros(ny, nx, dtype=torch.int8, device=DEV)
+    macc_g = torch.zeros(ny, nx, dtype=torch.float64, device=DEV)
+    for (lo, hi) in [(0, K), (3, 5), (K, K), (1, 0)]:
+        fl_c, m_c = O.flag(go, po, model, B, q0, q1, q2 if twod else None, frames, K, lo, hi, tol,
+                           acc_c, macc_c)
+        fl_g = torch.empty(ny, nx, dtype=torch.int8, device=DEV)
+        m_g = torch.empty(ny, nx, dtype=torch.float64, device=DEV)
+        S.adj_flag(gs, ps, Bd, qd, fd, K, lo, hi, tol, fl_g, m_g, acc_g, macc_g)
+        assert np.array_equal(host(fl_g), fl_c)
+        assert np.array_equal(host(m_g), m_c)
+    assert np.array_equal(host(acc_g), acc_c) and np.array_equal(host(macc_g), macc_c)
+
+
+def test_window_matches_oracle(oracle, S):
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        t0 = 0.0
+        tf = float(rng.choice([3600.0, 7200.0, 10800.0, 1000.0 / 3.0]))
+        K = int(rng.integers(1, 70))
+        ts = float(rng.uniform(t0, tf)) if rng.random() < 0.7 else float(rng.choice([t0, tf]))
+        t = float(rng.uniform(t0, tf * 1.05)) if rng.random() < 0.8 else t0 + int(rng.integers(0, K + 1)) * (tf - t0) / K
+        w = oracle.window(t, t0, ts, tf, K)
+        assert S.adj_window(t, t0, ts, tf, K) == (w if w is not None else (1, 0))
+
+
+# --------------------------------------------------------------------------
+def _run_pair(O, S, go, gs, model, B, eta0, target, t0, ts, tf, K, tol, flag_every=1):
+    ncomp = 3 if go.ny > 1 else 2
+    rc = O.run(go, O.Params(), model, B, eta0, target, t0, ts, tf, K, tol, flag_every=flag_every)
+    ps = S.Params(model=S.NONLINEAR if go.ny > 1 else S.LINEAR)
+    ny, nx = go.ny, go.nx
+    frames = torch.zeros(K + 1, ncomp, ny, nx, dtype=torch.float64, device=DEV)
+    q_out = [torch.zeros(ny, nx, dtype=torch.float64, device=DEV) for _ in range(ncomp)]
+    flags_at = torch.zeros(K + 1, ny, nx, dtype=torch.int8, device=DEV)
+    acc = torch.zeros(ny, nx, dtype=torch.int8, device=DEV)
+    macc = torch.zeros(ny, nx, dtype=torch.float64, device=DEV)
+    Bd, ed = dev(B.reshape(ny, nx)), dev(eta0.reshape(ny, nx))
+    pb = S.make_problem(gs, ps, Bd, ed, target, t0, ts, tf, K, tol, frames, q_out, flags_at, acc, macc,
+                        flag_every=flag_every)
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, dtype=torch.float64, device=DEV)
+    res = S.swe_run(pb, ws)
+    return rc, res, host(frames), [host(x) for x in q_out], host(flags_at), host(acc), host(macc)
+
+
+def _flags_match(fg, fc, maxip_c, tol):
+    """Flags equal except where the oracle's max inner product is within 1e-12 of tol."""
+    band = np.abs(maxip_c - tol) <= 1e-12 * tol
+    return np.array_equal(fg[~band], fc[~band])
+
+
+def test_run_1d_parity(oracle, S):
+    O = oracle
+    n = 2000
+    s = I.shelf1d(n, seed=0)
+    go, gs = pair_grids(O, S, n, 1, s.dx, 1.0, x_lo=s.x_lo)
+    rc, res, frames, q, flags_at, acc, macc = _run_pair(O, S, go, gs, O.LINEAR, s.B, s.eta0, s.target,
+                                                         0.0, 0.0, 3600.0, 20, 1e-3)
+    assert res.n_sub == rc.n_sub and res.n_adj_steps == rc.n_adj_steps
+    assert res.n_fwd_steps == rc.n_fwd_steps and res.n_rejected == rc.n_rejected
+    assert res.t_end == rc.t_end
+    assert close(frames, rc.frames)
+    assert close(q[0].ravel(), rc.q[0].ravel()) and close(q[1].ravel(), rc.q[1].ravel())
+    assert close(macc.ravel(), rc.maxip_acc.ravel())
+    assert _flags_match(acc.ravel(), rc.flag_acc.ravel(), rc.maxip_acc.ravel(), 1e-3)
+    assert rc.flag_acc.any()
+
+
+def test_run_2d_parity(oracle, S):
+    O = oracle
+    n = 96
+    b = I.basin(n, 3)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    rc, res, frames, q, flags_at, acc, macc = _run_pair(O, S, go, gs, O.NONLINEAR, b.B, b.eta0,
+                                                         (b.target[0], b.target[1], 60e3),
+                                                         0.0, 3600.0, 7200.0, 16, 1e-4)
+    assert res.n_sub == rc.n_sub and res.n_fwd_steps == rc.n_fwd_steps and res.t_end == rc.t_end
+    assert res.n_flag_calls == rc.n_flag_calls
+    assert close(frames, rc.frames)
+    ok, exact = compare_nl(b.B, q, rc.q)
+    print(f"run 2d: bit-exact state={exact}")
+    assert ok
+    assert close(macc, rc.maxip_acc)
+    assert _flags_match(acc, rc.flag_acc, rc.maxip_acc, 1e-4)
+    for j in range(17):
+        assert np.array_equal(flags_at[j], rc.flags_at[j]) or _flags_match(flags_at[j], rc.flags_at[j], rc.maxip_acc, 1e-4)
+    assert rc.flag_acc.any()
+
+
+# --------------------------------------------------------------------------
+def test_full_size_1024_sampled_steps(oracle, S):
+    """The 1024^2 basin of the step benchmark, 4 steps at the benchmark's
+    launch configuration, every element compared."""
+    O = oracle
+    n = 1024
+    b = I.basin(n, 2)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    q = O.init_state(go, p, O.NONLINEAR, b.B, b.eta0)
+    dt = O.dt0(go, p, O.NONLINEAR, b.B, *q)
+    qc, cc = nl_steps_cpu(O, go, p, b.B, q, [dt] * 4)
+    qg, cg, _ = nl_steps_gpu(S, gs, S.Params(), b.B, q, [dt] * 4)
+    ok, exact = compare_nl(b.B, qg, qc)
+    print(f"1024^2: bit-exact={exact}")
+    assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
