@@ -1,0 +1,255 @@
+"""Benchmark of the hot path on one MI355X.
+
+Headline: FP64 cell-updates/s of the 2D nonlinear shallow-water step
+(f-wave Roe solver, MC limiter, transverse corrections, dry threshold, CFL
+reduction with device-side time-step control) on the 1024 x 1024 synthetic
+ocean basin, as absolute rate and as a fraction of the HBM roofline.  One
+"step" is one time-step attempt of the whole grid: the marching step kernel
+plus the device-side CFL control.
+
+Prints ONE JSON line.  Secondary figures (adjoint step, flagging pass, the
+4096^2 grid that does not fit in the last-level cache) go under "extra".
+
+usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 20] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+BYTES_PER_CELL_STEP = 56       # read h, hu, hv, B; write h, hu, hv (8 B each)
+METRIC = "cell-updates/s FP64 2D SWE step (% HBM roofline); batched/served scen/s + p99 vs plain"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("swe_device.h", "swe_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_1605_05320_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kind: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "step_nl_1024_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get(kind)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one device copy of known size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "the grid and scenario decompositions across GPUs are described, not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1605_05320_amd import inputs as I
+    from paper_1605_05320_amd import swe as S
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    S.lib()
+    dev = torch.device("cuda")
+    f64 = dict(dtype=torch.float64, device=dev)
+
+    n = args.n
+    b = I.basin(n, args.seed)
+    grid = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    prm = S.Params()
+    B = torch.tensor(b.B, **f64)
+    eta0 = torch.tensor(b.eta0, **f64)
+    qa = [torch.empty(n, n, **f64) for _ in range(3)]
+    qb = [torch.empty(n, n, **f64) for _ in range(3)]
+    S.swe_init(grid, prm, B, eta0, qa)
+    spd = torch.zeros(1, dtype=torch.int64, device=dev)
+    S.swe_max_speed(grid, prm, B, qa, 0, spd)
+    dt0 = prm.cfl_desired / float(spd.view(torch.float64).item())
+    ctl = S.new_ctl()
+    S.swe_ctl_set(ctl, 0.0, dt0, 1.0e30, 0)     # open-ended segment: every attempt runs
+
+    stream = torch.cuda.current_stream()
+    S.swe_advance(grid, prm, B, qa, qb, ctl, args.warmup)
+    torch.cuda.synchronize()
+    c0 = S.read_ctl(ctl)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    S.swe_advance(grid, prm, B, qa, qb, ctl, args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    c1 = S.read_ctl(ctl)
+    accepted = c1.n_accepted - c0.n_accepted
+    rejected = c1.n_rejected - c0.n_rejected
+    cells = n * n
+    value = cells * accepted / (ms * 1e-3)
+    ms_per_step = ms / args.steps
+
+    # dominant kernel: the marching step.  Under device-side control every
+    # attempt is exactly one launch of it, so its average launch duration is
+    # the timed region over the attempts (HIP events on the launch stream).
+    k_us = ms_per_step * 1e3
+    algo_bytes = BYTES_PER_CELL_STEP * cells
+    achieved = algo_bytes / (k_us * 1e-6) / 1e9
+    traffic = load_traffic("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_march2d<NL>", "kernel_avg_us": round(k_us, 3),
+                "algorithmic_bytes_per_launch": algo_bytes}
+
+    extra = {"accepted_steps": accepted, "rejected_steps": rejected, "t_sim_s": round(c1.t, 3),
+             "wall_s": round(t_wall, 4)}
+    if not args.no_extra:
+        extra.update(secondary(S, torch, I, np, f64))
+
+    if args.copy_probe:
+        # one copy of known size, for scaling the HBM counters
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        extra["copy_probe_bytes"] = src.numel() * 8
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(b, n, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D nonlinear shallow water, {n}x{n} synthetic ocean basin "
+                               f"(seed {args.seed}: 4000 m plain, tanh shelf, 20 seamounts, dry land), "
+                               "1 m elliptical Gaussian source, f-wave Roe + MC limiter + transverse, "
+                               "dry tol 1e-3 m, CFL 0.9 with device-side dt control",
+                   "nx": n, "ny": n, "dx_m": b.grid.dx},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _time_events(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    z.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(z) * 1e-3 / reps
+
+
+def secondary(S, torch, I, np, f64):
+    out = {}
+    # adjoint step at 1024^2 (linearized, f-wave, transverse)
+    n = 1024
+    b = I.basin(n, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **f64)
+    q = [torch.zeros(n, n, **f64) for _ in range(3)]
+    r = [torch.empty(n, n, **f64) for _ in range(3)]
+    S.adj_target(g, p, B, b.target[0], b.target[1], 20e3, S.GAUSS, q)
+    t = _time_events(torch, lambda: S.adj_step(g, p, B, q, r, 1.0), 200)
+    out["adj_step_1024_cell_updates_per_s"] = n * n / t
+    out["adj_step_1024_us"] = t * 1e6
+    # flagging pass at 512^2, 34-frame window (the widest window of the
+    # adjoint-flagging workload), all cells wet-checked
+    n = 512
+    b = I.basin(n, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    B = torch.tensor(b.B, **f64)
+    K = 64
+    frames = torch.randn(K + 1, 3, n, n, **f64) * 1e-3
+    q = [torch.tensor(np.maximum(0.0, -b.B) + 0.0, **f64), torch.zeros(n, n, **f64), torch.zeros(n, n, **f64)]
+    fl = torch.empty(n, n, dtype=torch.int8, device=B.device)
+    acc = torch.zeros(n, n, dtype=torch.int8, device=B.device)
+    macc = torch.zeros(n, n, **f64)
+    t = _time_events(torch, lambda: S.adj_flag(g, p, B, q, frames, K, 30, 63, 1e-4, fl, None, acc, macc), 100)
+    W = 34
+    fbytes = n * n * (32 + 24 * W + 1 + 1 + 1 + 16)
+    out["flag_512_w34_us"] = t * 1e6
+    out["flag_512_w34_GBs"] = fbytes / t / 1e9
+    # the 4096^2 grid (~0.9 GB working set, beyond the 256 MB last-level cache)
+    n = 4096
+    b = I.basin(n, 2)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    B = torch.tensor(b.B, **f64)
+    e = torch.tensor(b.eta0, **f64)
+    qa = [torch.empty(n, n, **f64) for _ in range(3)]
+    qb = [torch.empty(n, n, **f64) for _ in range(3)]
+    S.swe_init(g, p, B, e, qa)
+    spd = torch.zeros(1, dtype=torch.int64, device=B.device)
+    S.swe_max_speed(g, p, B, qa, 0, spd)
+    dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
+    t = _time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), 40)
+    out["step_4096_cell_updates_per_s"] = n * n / t
+    out["step_4096_us"] = t * 1e6
+    out["step_4096_algorithmic_GBs"] = BYTES_PER_CELL_STEP * n * n / t / 1e9
+    del qa, qb, B, e
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(b, n, budget_s):
+    """The CPU oracle (plain C, fp64, OpenMP over rows) on the same input:
+    a bounded number of steps of the same 1024^2 grid."""
+    import numpy as np
+    from oracle import oracle as O
+    g = O.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    h, hu, hv = O.init_state(g, p, O.NONLINEAR, b.B, b.eta0)
+    dt = O.dt0(g, p, O.NONLINEAR, b.B, h, hu, hv)
+    t = time.perf_counter()
+    h, hu, hv, cfl, _ = O.swe_step(g, p, b.B, h, hu, hv, dt)
+    t1 = time.perf_counter() - t
+    m = int(max(2, min(200, budget_s / max(t1, 1e-6))))
+    t = time.perf_counter()
+    for _ in range(m):
+        dt = dt * p.cfl_desired / cfl
+        h, hu, hv, cfl, _ = O.swe_step(g, p, b.B, h, hu, hv, dt)
+    el = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    del np
+    return {"value": n * n * m / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} steps of the {n}x{n} basin after 1 warm-up step ({el:.1f} s), "
+                      f"OpenMP over rows"}
+
+
+if __name__ == "__main__":
+    main()

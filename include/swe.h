@@ -180,6 +180,60 @@ SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const d
                     int32_t k_hi, double tol, int8_t *flags, double *maxip,
                     int8_t *flag_acc, double *maxip_acc, void *stream);
 
+/*
+ * Device-side time-step control (the CFL rule of swe_run, phase B), so that a
+ * sequence of forward steps needs no host round-trip and can be captured in
+ * a HIP graph.  The control block lives in device memory; the state
+ * alternates between two plane sets a (cur = 0) and b (cur = 1).
+ * After each attempt of length dt with Courant number cfl:
+ *   cfl > cfl_max: rejected, dt = dt*cfl_desired/cfl;
+ *   else accepted: cur ^= 1, t = (final ? t_out : t + dt),
+ *        dt = dt*cfl_desired/cfl (unchanged if cfl = 0), done = final;
+ * and the next dt is clamped to t_out - t (setting final) unless done.
+ * Attempts while done do nothing.  Each step launch first applies the rule
+ * to the previous attempt (whose Courant number is complete by then), so an
+ * attempt costs exactly one kernel launch; swe_advance ends with one small
+ * kernel that resolves the last attempt into ctl->s.
+ */
+typedef struct {
+    double t;               /* time of the current state */
+    double dt;              /* length of the next attempt */
+    double t_out;           /* attempts never step past this time */
+    int32_t cur;            /* 0: state in a, 1: state in b */
+    int32_t final_step;     /* the next attempt ends exactly at t_out */
+    int32_t done;           /* t == t_out */
+    int32_t last_accepted;  /* the last attempt was accepted */
+    int32_t n_accepted, n_rejected;
+} swe_ctl_state;
+
+typedef struct {
+    swe_ctl_state s;        /* state after the last attempt (valid between swe_advance calls) */
+    uint64_t cfl_bits;      /* Courant number of the last attempt */
+    int32_t n_clamped, n_nonfinite;
+    swe_ctl_state slot[2];  /* kernel-internal: state of the running attempts */
+    uint64_t ring[3];       /* kernel-internal: Courant numbers of the running attempts */
+} swe_ctl;
+
+/* swe_ctl_set - (device) ctl := {t, dt clamped to t_out - t, t_out, cur,
+ * counters zero}.  Enqueued as a kernel (graph-safe). */
+SWE_API swe_status swe_ctl_set(swe_ctl *ctl, double t, double dt, double t_out, int32_t cur,
+                               void *stream);
+
+/* swe_ctl_retarget - (device) start a new segment: t_out := t_out, done := 0,
+ * dt re-clamped; t, dt, cur and the counters are kept. */
+SWE_API swe_status swe_ctl_retarget(swe_ctl *ctl, double t_out, void *stream);
+
+/*
+ * swe_advance - n_attempts forward step attempts (model of prm: nonlinear
+ * 2D or linear 1D) under the device-side control of `ctl`, each one a
+ * swe_step from the current plane set into the other followed by the control
+ * step above.  Enqueue only; read the control block back to see t, cur and
+ * the counters.  a and b must not alias.
+ */
+SWE_API swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double *B,
+                               swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_attempts,
+                               void *stream);
+
 /* Full problem of the two-phase driver. */
 typedef struct {
     swe_grid grid;

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "swe.h"
@@ -31,13 +32,26 @@ swe_status fail(swe_status st, const char *fmt, ...)
             return fail(SWE_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));           \
     } while (0)
 
-int default_ly(int ny)
+int default_ly(int nx, int ny)
 {
     // rows marched per wavefront: long enough to amortise the 2 halo rows on
-    // each side, short enough to give the chip >= 2 waves per SIMD
-    if (ny >= 4096) return 64;
-    if (ny >= 2048) return 32;
-    return 16;
+    // each side, short enough to give the chip >= 2 waves per SIMD.
+    // SWE_MARCH_ROWS overrides it (tuning sweeps).
+    static int forced = -1;
+    if (forced < 0) {
+        const char *e = std::getenv("SWE_MARCH_ROWS");
+        int v = e ? std::atoi(e) : 0;
+        forced = (v >= 1 && v <= 4096) ? v : 0;
+    }
+    if (forced > 0) return forced;
+    // about 1.5 resident wavefronts per SIMD (1024 SIMDs; the step kernel
+    // holds 2 per SIMD), at least 8 rows to amortise the 2.5 rows of warm-up,
+    // at most 32 (measured flat beyond)
+    long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
+    long long ly = (strips * ny + 767) / 1536;
+    if (ly < 8) ly = 8;
+    if (ly > 32) ly = 32;
+    return (int)ly;
 }
 
 swe_status check_grid(const swe_grid *g)
@@ -101,7 +115,7 @@ swe::KParams make_kparams(const swe_grid *g, const swe_params *p, const double *
 {
     swe::KParams k;
     std::memset(&k, 0, sizeof k);
-    k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch; k.ly = default_ly(g->ny);
+    k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch; k.ly = default_ly(g->nx, g->ny);
     for (int c = 0; c < 4; ++c) k.bc[c] = g->bc[c];
     k.order = p->order; k.transverse = p->transverse;
     k.dx = g->dx; k.dy = g->ny > 1 ? g->dy : 1.0; k.dt = dt;
@@ -215,6 +229,55 @@ static double snap(double r)
 {
     double rr = std::nearbyint(r);
     return std::fabs(r - rr) <= 1e-9 ? rr : r;
+}
+
+swe_status swe_ctl_set(swe_ctl *ctl, double t, double dt, double t_out, int32_t cur, void *stream)
+{
+    if (!ctl) return fail(SWE_E_INVAL, "ctl is NULL");
+    if (!std::isfinite(t) || !std::isfinite(t_out) || !(t_out >= t)) return fail(SWE_E_INVAL, "need finite t <= t_out");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SWE_E_INVAL, "dt must be finite and > 0");
+    if (cur != 0 && cur != 1) return fail(SWE_E_INVAL, "cur must be 0 or 1");
+    HIP_TRY(swe::launch_ctl_set(ctl, t, dt, t_out, cur, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+swe_status swe_ctl_retarget(swe_ctl *ctl, double t_out, void *stream)
+{
+    if (!ctl) return fail(SWE_E_INVAL, "ctl is NULL");
+    if (!std::isfinite(t_out)) return fail(SWE_E_INVAL, "t_out must be finite");
+    HIP_TRY(swe::launch_ctl_retarget(ctl, t_out, (hipStream_t)stream));
+    return SWE_OK;
+}
+
+swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
+                       swe_fields b, swe_ctl *ctl, int32_t n_attempts, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B || !ctl) return fail(SWE_E_INVAL, "B or ctl is NULL");
+    if ((st = check_fields(grid, a, "a")) != SWE_OK) return st;
+    if ((st = check_fields(grid, b, "b")) != SWE_OK) return st;
+    if ((st = check_alias(grid, a, b)) != SWE_OK) return st;
+    if (n_attempts < 0) return fail(SWE_E_INVAL, "n_attempts must be >= 0");
+    if (!(prm->cfl_desired > 0.0) || !(prm->cfl_max >= prm->cfl_desired))
+        return fail(SWE_E_INVAL, "need 0 < cfl_desired <= cfl_max");
+    int model = prm->model == SWE_NONLINEAR ? swe::MODEL_NL : swe::MODEL_LIN;
+    if (model == swe::MODEL_NL && grid->ny < 2) return fail(SWE_E_INVAL, "the nonlinear model needs ny >= 2");
+    if (model == swe::MODEL_LIN && grid->ny != 1) return fail(SWE_E_INVAL, "the linear model needs ny == 1");
+    swe::KParams k = make_kparams(grid, prm, B, a, b, 1.0, nullptr);
+    k.ctl = ctl;
+    k.cfl_desired = prm->cfl_desired;
+    k.cfl_max = prm->cfl_max;
+    k.n_clamped = &ctl->n_clamped;
+    k.n_nonfinite = &ctl->n_nonfinite;
+    hipStream_t s = (hipStream_t)stream;
+    for (int n = 0; n < n_attempts; ++n) {
+        k.attempt = n;
+        HIP_TRY(swe::launch_step(model, k, s));
+    }
+    if (n_attempts > 0) HIP_TRY(swe::launch_ctl_finish(ctl, n_attempts, prm->cfl_desired, prm->cfl_max, s));
+    return SWE_OK;
 }
 
 swe_status adj_window(double t, double t0, double ts, double tf, int32_t K, int32_t *k_lo, int32_t *k_hi)

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "swe.h"
+
 namespace swe {
 
 struct KParams;
@@ -31,6 +33,9 @@ struct CellParams {
 
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur, hipStream_t s);
+hipError_t launch_ctl_retarget(swe_ctl *c, double t_out, hipStream_t s);
+hipError_t launch_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max, hipStream_t s);
 hipError_t launch_target(const CellParams &C, double xc, double yc, double R, int shape, hipStream_t s);
 hipError_t launch_init(const CellParams &C, const double *eta0, int nonlinear, hipStream_t s);
 hipError_t launch_max_speed(const CellParams &C, const double *q0, const double *q1, const double *q2,

@@ -72,6 +72,7 @@ __device__ __forceinline__ void g_tilde(const Edge &e, const Edge &lo, const Edg
 template <class M>
 __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 {
+    if (!resolve_ctl(P)) return;
     const int lane = threadIdx.x;
     const int i = blockIdx.x * STRIP + lane - HALO;
     const int j0 = blockIdx.y * P.ly;
@@ -204,11 +205,11 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
     }
 
     cfl = wave_max(cfl);
-    if (lane == 0 && P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
     unsigned long long mc = __ballot(nclamp > 0), mb = __ballot(nbad > 0);
     if (lane == 0) {
         if (mc && P.n_clamped) atomicAdd(P.n_clamped, __popcll(mc));
         if (mb && P.n_nonfinite) atomicAdd(P.n_nonfinite, __popcll(mb));
+        if (P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
     }
 }
 
@@ -216,6 +217,7 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 template <class M>
 __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
 {
+    if (!resolve_ctl(P)) return;
     const int lane = threadIdx.x;
     const int i = blockIdx.x * STRIP + lane - HALO;
     const double nu = P.dt / P.dx;
@@ -257,6 +259,51 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
         for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nu * fabs(x.s[p]));
     cfl = wave_max(cfl);
     if (lane == 0 && P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+}
+
+// ---------------------------------------------------------------------------
+// Device-side step control (single thread).
+// ---------------------------------------------------------------------------
+__global__ void k_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    swe_ctl_state S;
+    S.t = t;
+    S.dt = dt;
+    S.t_out = t_out;
+    S.cur = cur;
+    S.final_step = 0;
+    S.done = 0;
+    S.last_accepted = 0;
+    S.n_accepted = 0;
+    S.n_rejected = 0;
+    ctl_clamp(S);
+    c->s = S;
+    c->cfl_bits = 0;
+    c->n_clamped = 0;
+    c->n_nonfinite = 0;
+    c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
+}
+
+__global__ void k_ctl_retarget(swe_ctl *c, double t_out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    swe_ctl_state S = c->s;
+    S.t_out = t_out;
+    S.done = 0;
+    S.last_accepted = 0;
+    ctl_clamp(S);
+    c->s = S;
+}
+
+// Resolve the last of n attempts into ctl->s and clear the Courant slots.
+__global__ void k_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0 || n < 1) return;
+    unsigned long long bits = c->ring[(n - 1) % 3];
+    c->s = ctl_apply(c->slot[(n - 1) & 1], __longlong_as_double((long long)bits), cfl_desired, cfl_max);
+    c->cfl_bits = bits;
+    c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -393,6 +440,24 @@ hipError_t launch_step(int model, const KParams &P, hipStream_t s)
         else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, P);
         else return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(1), 0, s, c, t, dt, t_out, cur);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_retarget(swe_ctl *c, double t_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_retarget, dim3(1), dim3(1), 0, s, c, t_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(1), 0, s, c, n, cfl_desired, cfl_max);
     return hipGetLastError();
 }
 

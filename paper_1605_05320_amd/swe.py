@@ -58,7 +58,26 @@ class swe_result(C.Structure):
                 ("dt_adj", C.c_double), ("t_end", C.c_double)]
 
 
+class swe_ctl_state(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("t_out", C.c_double),
+                ("cur", C.c_int32), ("final_step", C.c_int32), ("done", C.c_int32),
+                ("last_accepted", C.c_int32), ("n_accepted", C.c_int32), ("n_rejected", C.c_int32)]
+
+
+class swe_ctl(C.Structure):
+    _fields_ = [("s", swe_ctl_state), ("cfl_bits", C.c_uint64), ("n_clamped", C.c_int32),
+                ("n_nonfinite", C.c_int32), ("slot", swe_ctl_state * 2), ("ring", C.c_uint64 * 3)]
+
+    # flat access to the resolved state
+    def __getattr__(self, name):
+        if name in ("t", "dt", "t_out", "cur", "final_step", "done", "last_accepted", "n_accepted",
+                    "n_rejected"):
+            return getattr(self.s, name)
+        raise AttributeError(name)
+
+
 SCALARS_BYTES = 16  # swe_scalars: uint64 cfl_bits, int32 n_clamped, int32 n_nonfinite
+CTL_BYTES = C.sizeof(swe_ctl)
 
 _lib = None
 
@@ -72,7 +91,7 @@ def lib():
                               "(python -m paper_1605_05320_amd.build)")
         L = C.CDLL(LIB_PATH)
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
-                     "adj_flag", "swe_run"):
+                     "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_last_error.restype = C.c_char_p
@@ -207,3 +226,28 @@ def swe_run(pb: swe_problem, workspace, stream=None) -> swe_result:
     _check(lib().swe_run(C.byref(pb), _ptr(workspace), C.c_size_t(nbytes), C.byref(res),
                          _stream(stream)))
     return res
+
+
+def new_ctl(device="cuda"):
+    """A device buffer for one swe_ctl (uninitialised; use swe_ctl_set)."""
+    import torch
+    return torch.zeros(CTL_BYTES, dtype=torch.uint8, device=device)
+
+
+def read_ctl(ctl_tensor) -> swe_ctl:
+    raw = bytes(ctl_tensor.cpu().numpy().tobytes())
+    return swe_ctl.from_buffer_copy(raw)
+
+
+def swe_ctl_set(ctl, t, dt, t_out, cur=0, stream=None):
+    _check(lib().swe_ctl_set(_ptr(ctl), C.c_double(t), C.c_double(dt), C.c_double(t_out),
+                             C.c_int32(cur), _stream(stream)))
+
+
+def swe_ctl_retarget(ctl, t_out, stream=None):
+    _check(lib().swe_ctl_retarget(_ptr(ctl), C.c_double(t_out), _stream(stream)))
+
+
+def swe_advance(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, stream=None):
+    _check(lib().swe_advance(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
+                             _ptr(ctl), C.c_int32(n_attempts), _stream(stream)))

@@ -344,3 +344,71 @@ def test_full_size_1024_sampled_steps(oracle, S):
     ok, exact = compare_nl(b.B, qg, qc)
     print(f"1024^2: bit-exact={exact}")
     assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
+
+
+# --------------------------------------------------------------------------
+def _oracle_controlled(O, g, p, B, q, dt, t, t_out, n_attempts, cfl_d, cfl_max):
+    """Host mirror of the device-side control rule (same rule as the driver)."""
+    fin = False
+    if dt >= t_out - t:
+        dt, fin = t_out - t, True
+    done, acc, rej = False, 0, 0
+    for _ in range(n_attempts):
+        if done:
+            continue
+        h, hu, hv, cfl, _ = O.swe_step(g, p, B, *q, dt)
+        if cfl > cfl_max:
+            rej += 1
+            dt = dt * cfl_d / cfl
+        else:
+            acc += 1
+            q = [h, hu, hv]
+            t = t_out if fin else t + dt
+            done = fin
+            if cfl > 0.0:
+                dt = dt * cfl_d / cfl
+        if not done:
+            fin = False
+            if dt >= t_out - t:
+                dt, fin = t_out - t, True
+    return q, t, dt, acc, rej, done
+
+
+def test_device_controlled_steps_match_oracle(oracle, S):
+    """swe_advance (device-side CFL rule, rejections, clamping to the output
+    time, no-op attempts once done, retargeting) against the host mirror."""
+    O = oracle
+    n = 120
+    b = I.basin(n, 12)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    po = O.Params(cfl_desired=0.9, cfl_max=0.95)
+    ps = S.Params(cfl_desired=0.9, cfl_max=0.95)
+    q = O.init_state(go, po, O.NONLINEAR, b.B, b.eta0 * 30.0)
+    dt0 = O.dt0(go, po, O.NONLINEAR, b.B, *q)
+    t_out = 25.3 * dt0
+    qc, t_c, dt_c, acc_c, rej_c, done_c = _oracle_controlled(O, go, po, b.B, q, 1.3 * dt0, 0.0, t_out, 40,
+                                                             0.9, 0.95)
+    assert rej_c >= 1 and done_c
+    Bd = dev(b.B)
+    a = [dev(x) for x in q]
+    bb = [torch.empty_like(x) for x in a]
+    ctl = S.new_ctl()
+    S.swe_ctl_set(ctl, 0.0, 1.3 * dt0, t_out, 0)
+    S.swe_advance(gs, ps, Bd, a, bb, ctl, 40)
+    c = S.read_ctl(ctl)
+    assert (c.n_accepted, c.n_rejected, c.done, c.t) == (acc_c, rej_c, 1, t_c)
+    assert c.dt == dt_c
+    cur = a if c.cur == 0 else bb
+    ok, exact = compare_nl(b.B, [host(x) for x in cur], qc)
+    assert ok
+    # second segment
+    t_out2 = t_out + 7.7 * dt0
+    qc2, t_c2, dt_c2, acc2, rej2, _ = _oracle_controlled(O, go, po, b.B, qc, dt_c, t_c, t_out2, 12, 0.9, 0.95)
+    S.swe_ctl_retarget(ctl, t_out2)
+    S.swe_advance(gs, ps, Bd, a, bb, ctl, 12)
+    c = S.read_ctl(ctl)
+    assert c.t == t_c2 and c.dt == dt_c2 and c.n_accepted == acc_c + acc2
+    cur = a if c.cur == 0 else bb
+    ok, exact = compare_nl(b.B, [host(x) for x in cur], qc2)
+    print(f"controlled: {c.n_accepted} accepted, {c.n_rejected} rejected, bit-exact={exact}")
+    assert ok
