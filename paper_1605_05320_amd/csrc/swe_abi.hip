@@ -32,11 +32,27 @@ swe_status fail(swe_status st, const char *fmt, ...)
             return fail(SWE_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));           \
     } while (0)
 
+// Wavefront slots of the step kernel on the current device: 4 SIMDs per CU,
+// 2 resident wavefronts per SIMD (register-limited).
+int wave_slots()
+{
+    static int slots = 0;
+    if (slots == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        slots = cus * 4 * 2;
+    }
+    return slots;
+}
+
+// Rows marched per wavefront.  The smallest height of at least 8 rows (the
+// warm-up costs 2.5 rows) whose launch fits in one wave of resident
+// wavefronts; 32 when the grid is too large for that (measured flat beyond).
+// SWE_MARCH_ROWS overrides it (tuning sweeps).
 int default_ly(int nx, int ny)
 {
-    // rows marched per wavefront: long enough to amortise the 2 halo rows on
-    // each side, short enough to give the chip >= 2 waves per SIMD.
-    // SWE_MARCH_ROWS overrides it (tuning sweeps).
     static int forced = -1;
     if (forced < 0) {
         const char *e = std::getenv("SWE_MARCH_ROWS");
@@ -44,14 +60,26 @@ int default_ly(int nx, int ny)
         forced = (v >= 1 && v <= 4096) ? v : 0;
     }
     if (forced > 0) return forced;
-    // about 1.5 resident wavefronts per SIMD (1024 SIMDs; the step kernel
-    // holds 2 per SIMD), at least 8 rows to amortise the 2.5 rows of warm-up,
-    // at most 32 (measured flat beyond)
     long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
-    long long ly = (strips * ny + 767) / 1536;
-    if (ly < 8) ly = 8;
-    if (ly > 32) ly = 32;
-    return (int)ly;
+    for (int ly = 8; ly <= 32; ++ly)
+        if (strips * ((ny + ly - 1) / ly) <= wave_slots()) return ly;
+    return 32;
+}
+
+// XCD-aware tile placement pays when all wavefronts of the launch are
+// resident together (halo rows then come from the shared L2); for larger
+// launches it concentrates each XCD on a narrow band of memory and is off.
+// SWE_XCD_REMAP=0/1 forces it.
+int xcd_remap_for(int nx, int ny, int ly)
+{
+    static int forced = -2;
+    if (forced == -2) {
+        const char *e = std::getenv("SWE_XCD_REMAP");
+        forced = e ? (std::atoi(e) != 0) : -1;
+    }
+    if (forced >= 0) return forced;
+    long long waves = (long long)((nx + swe::STRIP - 1) / swe::STRIP) * ((ny + ly - 1) / ly);
+    return waves <= wave_slots() ? 1 : 0;
 }
 
 swe_status check_grid(const swe_grid *g)
@@ -116,6 +144,7 @@ swe::KParams make_kparams(const swe_grid *g, const swe_params *p, const double *
     swe::KParams k;
     std::memset(&k, 0, sizeof k);
     k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch; k.ly = default_ly(g->nx, g->ny);
+    k.xcd_remap = xcd_remap_for(g->nx, g->ny, k.ly);
     for (int c = 0; c < 4; ++c) k.bc[c] = g->bc[c];
     k.order = p->order; k.transverse = p->transverse;
     k.dx = g->dx; k.dy = g->ny > 1 ? g->dy : 1.0; k.dt = dt;

@@ -17,13 +17,54 @@
 
 namespace swe {
 
-// Per-row correction flux of a y-edge with its transverse terms.
+// A-dQ and edge type of the x-edge east of this lane's cell (lane + 1).
+struct XFl {
+    double am[3];
+    int t;
+};
+
+// What the row below still needs of a y-edge once it becomes the southern
+// edge of the current row: its waves (limiter of the next y-edge) and its
+// upward fluctuation (update and transverse terms).
+struct YPrev {
+    double z[3][3];
+    double ap[3];
+    int type;
+};
+
 template <class M>
-__device__ __forceinline__ void g_tilde(const Edge &e, const Edge &lo, const Edge &hi, const KParams &P,
-                                        double nuy, double hnux,
-                                        const double *t0, int ty0, const double *t1, int ty1,
-                                        const double *t2, int ty2, const double *t3, int ty3,
-                                        double G[3])
+__device__ __forceinline__ void keep_yprev(const Edge &e, YPrev &y)
+{
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y.z[p][c] = (p < M::NW && M::zc(p, c)) ? e.z[p][c] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y.ap[c] = e.ap[c];
+    y.type = e.type;
+}
+
+// The state of the row being updated (the rest of its cell data is no longer needed).
+struct QRow {
+    double q[3];
+    bool upd;
+};
+
+template <class M>
+__device__ __forceinline__ void keep_qrow(const typename M::Cell &c, QRow &r)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) r.q[k] = M::q(c, k);
+    r.upd = M::updates(c);
+}
+
+// y-edge correction flux from a YPrev-style lower neighbour.
+template <class M>
+__device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const Edge &hi, const KParams &P,
+                                          double nuy, double hnux,
+                                          const double *t0, int ty0, const double *t1, int ty1,
+                                          const double *t2, int ty2, const double *t3, int ty3,
+                                          double G[3])
 {
     G[0] = 0.0; G[1] = 0.0; G[2] = 0.0;
     if (e.type != E_WET) return;
@@ -74,8 +115,11 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 {
     if (!resolve_ctl(P)) return;
     const int lane = threadIdx.x;
-    const int i = blockIdx.x * STRIP + lane - HALO;
-    const int j0 = blockIdx.y * P.ly;
+    const int G = P.nstrips * P.nchunks;
+    const int t = P.xcd_remap ? xcd_logical_block(blockIdx.x, G) : blockIdx.x;
+    const int strip = t / P.nchunks, chunk = t - strip * P.nchunks;
+    const int i = strip * STRIP + lane - HALO;
+    const int j0 = chunk * P.ly;
     const int j1 = min(j0 + P.ly, P.ny);
     const double nux = P.dt / P.dx, nuy = P.dt / P.dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
@@ -87,38 +131,42 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
     int nclamp = 0, nbad = 0;
 
     using Cell = typename M::Cell;
-    Cell cA = M::load(P, i, j0 - 2);
-    Cell cB = M::load(P, i, j0 - 1);
-    Cell cC = M::load(P, i, j0);
-    Cell cD = M::load(P, i, j0 + 1);
-
-    Edge yS, yN, xCur;
-    double G_S[3];
-    double xCurE_am[3];
-    int xCurE_t;
+    QRow qC;                 // row r (being updated)
+    Cell cD;                 // row r + 1
+    YPrev yS;                // y-edge r - 1/2
+    Edge yN, xCur;           // y-edge r + 1/2, x-edge of row r
+    XFl xCurE;               // its east neighbour's A-dQ
+    double G_S[3];           // G of edge r - 1/2
     {
-        Edge yS2, xPrev;
+        Cell cA = M::load(P, i, j0 - 2);
+        Cell cB = M::load(P, i, j0 - 1);
+        Cell cC = M::load(P, i, j0);
+        cD = M::load(P, i, j0 + 1);
+        Edge yS2, yS0, xPrev;
         M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
-        M::solve(cB, cC, true, P, yS);             // y-edge j0 - 1/2
+        M::solve(cB, cC, true, P, yS0);            // y-edge j0 - 1/2
         M::solve(cC, cD, true, P, yN);             // y-edge j0 + 1/2
         Cell lB = M::shfl_cell(cB, up);
         M::solve(lB, cB, false, P, xPrev);         // x-edge (i - 1/2, j0 - 1)
         Cell lC = M::shfl_cell(cC, up);
         M::solve(lC, cC, false, P, xCur);          // x-edge (i - 1/2, j0)
-        double xPrevE_am[3];
+        XFl ePrev;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            xPrevE_am[c] = shfl(xPrev.am[c], dn);
-            xCurE_am[c] = shfl(xCur.am[c], dn);
+            ePrev.am[c] = shfl(xPrev.am[c], dn);
+            xCurE.am[c] = shfl(xCur.am[c], dn);
         }
-        int xPrevE_t = shfl(xPrev.type, dn);
-        xCurE_t = shfl(xCur.type, dn);
-        g_tilde<M>(yS, yS2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, xPrevE_am, xPrevE_t,
-                   xCur.ap, xCur.type, xCurE_am, xCurE_t, G_S);
-        if (core && j0 < P.ny) {
+        ePrev.t = shfl(xPrev.type, dn);
+        xCurE.t = shfl(xCur.type, dn);
+        YPrev lo2;
+        keep_yprev<M>(yS2, lo2);
+        g_tilde_r<M>(yS0, lo2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
+                     xCur.ap, xCur.type, xCurE.am, xCurE.t, G_S);
+        if (core)
 #pragma unroll
-            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yS.s[p]));
-        }
+            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yS0.s[p]));
+        keep_yprev<M>(yS0, yS);
+        keep_qrow<M>(cC, qC);
     }
 
     for (int r = j0; r < j1; ++r) {
@@ -127,15 +175,20 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
         M::solve(cD, cE, true, P, yNN);            // y-edge r + 3/2
         Cell lD = M::shfl_cell(cD, up);
         M::solve(lD, cD, false, P, xNext);         // x-edge (i - 1/2, r + 1)
-        double xNextE_am[3];
+        XFl xNextE;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xNextE_am[c] = shfl(xNext.am[c], dn);
-        int xNextE_t = shfl(xNext.type, dn);
+        for (int c = 0; c < 3; ++c) xNextE.am[c] = shfl(xNext.am[c], dn);
+        xNextE.t = shfl(xNext.type, dn);
 
         // G(i, r + 1/2)
         double G_N[3];
-        g_tilde<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE_am, xCurE_t,
-                   xNext.ap, xNext.type, xNextE_am, xNextE_t, G_N);
+        {
+            YPrev lo;
+            // the lower neighbour of y-edge r + 1/2 is y-edge r - 1/2 (yS)
+            g_tilde_r<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE.am, xCurE.t,
+                         xNext.ap, xNext.type, xNextE.am, xNextE.t, G_N);
+            (void)lo;
+        }
 
         // F(i - 1/2, r): limiter from lanes -1/+1, transverse from the y-edges
         // of columns i-1 (lane - 1) and i (own).
@@ -166,9 +219,9 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
             double o[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                double qv = M::q(cC, c);
-                if (M::updates(cC)) {
-                    qv = qv - nux * (xCur.ap[c] + xCurE_am[c]);
+                double qv = qC.q[c];
+                if (qC.upd) {
+                    qv = qv - nux * (xCur.ap[c] + xCurE.am[c]);
                     qv = qv - nuy * (yS.ap[c] + yN.am[c]);
                     qv = qv - nux * (F_E[c] - F_W[c]);
                     qv = qv - nuy * (G_N[c] - G_S[c]);
@@ -193,15 +246,15 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 #pragma unroll
             for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yN.s[p]));
 
-        // roll the window down one row
-        yS = yN;
+        // move the window down one row, keeping only what is still needed
+        keep_yprev<M>(yN, yS);
         yN = yNN;
         xCur = xNext;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { xCurE_am[c] = xNextE_am[c]; G_S[c] = G_N[c]; }
-        xCurE_t = xNextE_t;
-        cC = cD;
+        xCurE = xNextE;
+        keep_qrow<M>(cD, qC);
         cD = cE;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G_S[c] = G_N[c];
     }
 
     cfl = wave_max(cfl);
@@ -435,9 +488,12 @@ hipError_t launch_step(int model, const KParams &P, hipStream_t s)
         else if (model == MODEL_LIN) hipLaunchKernelGGL(k_step1d<LIN1>, grid, block, 0, s, P);
         else return hipErrorInvalidValue;
     } else {
-        dim3 grid((P.nx + STRIP - 1) / STRIP, (P.ny + P.ly - 1) / P.ly);
-        if (model == MODEL_NL) hipLaunchKernelGGL(k_march2d<NL>, grid, block, 0, s, P);
-        else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, P);
+        KParams Q = P;
+        Q.nstrips = (P.nx + STRIP - 1) / STRIP;
+        Q.nchunks = (P.ny + P.ly - 1) / P.ly;
+        dim3 grid(Q.nstrips * Q.nchunks);
+        if (model == MODEL_NL) hipLaunchKernelGGL(k_march2d<NL>, grid, block, 0, s, Q);
+        else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, Q);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -13,7 +13,7 @@ import os
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libswe.so")
+LIB_PATH = os.environ.get("SWE_LIB") or os.path.join(HERE, "libswe.so")
 
 OK, E_INVAL, E_CFL, E_HIP, E_NOMEM, E_NONFINITE, E_NEGDEPTH = 0, -1, -2, -3, -4, -5, -6
 BC_WALL, BC_EXTRAP = 0, 1
