@@ -234,6 +234,71 @@ SWE_API swe_status swe_advance(const swe_grid *grid, const swe_params *prm, cons
                                swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_attempts,
                                void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched AMR level: many small patches (block-structured refinement, Sec. 1)
+ * advanced together with one level-wide time step.
+ * ------------------------------------------------------------------------ */
+
+/* One patch: nx x ny cells stored at planes + offset with row pitch nx; its
+ * own cell size and boundary conditions (walls for isolated patches). */
+typedef struct {
+    int64_t offset;
+    int32_t nx, ny;         /* 2 <= nx, ny */
+    int32_t bc[4];
+    double dx, dy;
+} swe_patch;
+
+typedef enum {
+    SWE_SCHED_STRIP = 0,    /* one patch strip (<= 60 columns) per wavefront */
+    SWE_SCHED_PACKED = 1    /* strips of equal row count packed side by side into 64 lanes,
+                               first-fit decreasing; jobs ordered longest first */
+} swe_schedule_kind;
+
+/*
+ * swe_level_schedule - (host) build the wavefront schedule of a level.
+ * A pass is one wavefront's work: up to 64 lanes, each lane a column of one
+ * patch strip (the strip's columns plus 2 ghost columns each side); all its
+ * patches are marched over `pass_rows` rows.  A job is a run of passes done by
+ * one wavefront; every patch lies within one job.
+ *   lanes:     n_passes*64 int64, lane = (patch << 32) | (role << 16) | (col + 32768),
+ *              role bit 0: output column, bit 1: its west edge counts for the
+ *              Courant number; -1 for an idle lane
+ *   pass_rows: n_passes int32;  job_pass: n_jobs+1 int32 (passes of job j are
+ *              job_pass[j] .. job_pass[j+1]-1)
+ * Call with null outputs to get the sizes.  Returns n_passes (>= 0) and sets
+ * *n_jobs, or a negative swe_status.  patches: host array.
+ */
+SWE_API int32_t swe_level_schedule(const swe_patch *patches, int32_t n_patches, int32_t kind,
+                                   int64_t *lanes, int32_t *pass_rows, int32_t *job_pass,
+                                   int32_t *n_jobs);
+
+/* A level on the device. */
+typedef struct {
+    int32_t n_patches, n_passes, n_jobs, reserved;
+    const swe_patch *patches;   /* device table */
+    const int64_t *lanes;       /* device, from swe_level_schedule */
+    const int32_t *pass_rows;   /* device */
+    const int32_t *job_pass;    /* device */
+    uint32_t *sync;             /* device, 4 words zeroed once by the caller (persistent mode) */
+} swe_level;
+
+/*
+ * swe_level_advance - n_steps step attempts of the whole level (nonlinear
+ * model) under device-side control `ctl` (the rule of swe_advance, with the
+ * Courant number the max over all patches).  persistent = 0: one launch per
+ * attempt, one wavefront per pass (graph-capturable).  persistent = 1: a
+ * single cooperative launch of at most one wavefront per resident slot runs
+ * all attempts, the wavefronts meeting at a grid barrier after each attempt;
+ * a barrier that does not open within a bounded spin sets sync[2] to nonzero
+ * and the launch ends early (the caller checks sync[2]; the state is then
+ * not a valid result).  Each patch is owned by one wavefront, so patches never
+ * exchange data within a launch.  State in a (cur = 0) / b (cur = 1); B: bottom
+ * planes of the level.  Enqueue only.
+ */
+SWE_API swe_status swe_level_advance(const swe_level *level, const swe_params *prm, const double *B,
+                                     swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_steps,
+                                     int32_t persistent, void *stream);
+
 /* Full problem of the two-phase driver. */
 typedef struct {
     swe_grid grid;

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe.so")
-SOURCES = ["swe_kernels.hip", "swe_abi.hip"]
+SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip"]
 
 # binary64 without contraction (results are defined op by op); packed FP32
 # instructions disabled.

@@ -13,9 +13,10 @@
 #include "swe_internal.h"
 
 namespace {
-
 thread_local char g_err[512] = "";
+}
 
+namespace swe {
 swe_status fail(swe_status st, const char *fmt, ...)
 {
     va_list ap;
@@ -24,6 +25,10 @@ swe_status fail(swe_status st, const char *fmt, ...)
     va_end(ap);
     return st;
 }
+} // namespace swe
+
+namespace {
+using swe::fail;
 
 #define HIP_TRY(expr)                                                                  \
     do {                                                                               \

@@ -8,6 +8,7 @@
 namespace swe {
 
 struct KParams;
+struct LevelArgs;
 
 enum { MODEL_NL = 0, MODEL_LIN = 1, MODEL_ADJ = 2 };
 
@@ -31,8 +32,14 @@ struct CellParams {
     double *o0, *o1, *o2;
 };
 
+// record a message for swe_last_error() and return st
+swe_status fail(swe_status st, const char *fmt, ...);
+
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_level_step(const KParams &P, const LevelArgs &L, hipStream_t s);
+hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s);
+int level_persistent_capacity();
 hipError_t launch_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur, hipStream_t s);
 hipError_t launch_ctl_retarget(swe_ctl *c, double t_out, hipStream_t s);
 hipError_t launch_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max, hipStream_t s);

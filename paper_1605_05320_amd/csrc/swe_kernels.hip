@@ -110,25 +110,20 @@ __device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const 
                              t3, ty3 == E_WET, G);
 }
 
+// The marching step of one wavefront: lane `lane` holds column i of the grid
+// G (its own patch in a batched level), rows j0 .. j1-1 are updated; the loop
+// runs to jend (uniform over the wavefront), rows from j1 on are computed but
+// neither stored nor counted.  core: the lane's cell is an output cell;
+// xedge_in: its west edge counts for the Courant number.
 template <class M>
-__global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
+__device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
+                                      int jend, bool core, bool xedge_in, double dx, double dy,
+                                      double &cfl, int &nclamp, int &nbad)
 {
-    if (!resolve_ctl(P)) return;
-    const int lane = threadIdx.x;
-    const int G = P.nstrips * P.nchunks;
-    const int t = P.xcd_remap ? xcd_logical_block(blockIdx.x, G) : blockIdx.x;
-    const int strip = t / P.nchunks, chunk = t - strip * P.nchunks;
-    const int i = strip * STRIP + lane - HALO;
-    const int j0 = chunk * P.ly;
-    const int j1 = min(j0 + P.ly, P.ny);
-    const double nux = P.dt / P.dx, nuy = P.dt / P.dy;
+    const double nux = P.dt / dx, nuy = P.dt / dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
-    const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
-    const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
     const int up = lane > 0 ? lane - 1 : 0;
     const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
-    double cfl = 0.0;
-    int nclamp = 0, nbad = 0;
 
     using Cell = typename M::Cell;
     QRow qC;                 // row r (being updated)
@@ -138,10 +133,10 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
     XFl xCurE;               // its east neighbour's A-dQ
     double G_S[3];           // G of edge r - 1/2
     {
-        Cell cA = M::load(P, i, j0 - 2);
-        Cell cB = M::load(P, i, j0 - 1);
-        Cell cC = M::load(P, i, j0);
-        cD = M::load(P, i, j0 + 1);
+        Cell cA = M::load(P, G, i, j0 - 2);
+        Cell cB = M::load(P, G, i, j0 - 1);
+        Cell cC = M::load(P, G, i, j0);
+        cD = M::load(P, G, i, j0 + 1);
         Edge yS2, yS0, xPrev;
         M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
         M::solve(cB, cC, true, P, yS0);            // y-edge j0 - 1/2
@@ -162,15 +157,16 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
         keep_yprev<M>(yS2, lo2);
         g_tilde_r<M>(yS0, lo2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
                      xCur.ap, xCur.type, xCurE.am, xCurE.t, G_S);
-        if (core)
+        if (core && j0 < j1)
 #pragma unroll
             for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yS0.s[p]));
         keep_yprev<M>(yS0, yS);
         keep_qrow<M>(cC, qC);
     }
 
-    for (int r = j0; r < j1; ++r) {
-        Cell cE = M::load(P, i, r + 2);
+    for (int r = j0; r < jend; ++r) {
+        const bool row_ok = r < j1;
+        Cell cE = M::load(P, G, i, r + 2);
         Edge yNN, xNext;
         M::solve(cD, cE, true, P, yNN);            // y-edge r + 3/2
         Cell lD = M::shfl_cell(cD, up);
@@ -180,15 +176,10 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
         for (int c = 0; c < 3; ++c) xNextE.am[c] = shfl(xNext.am[c], dn);
         xNextE.t = shfl(xNext.type, dn);
 
-        // G(i, r + 1/2)
+        // G(i, r + 1/2); the lower neighbour of y-edge r + 1/2 is y-edge r - 1/2
         double G_N[3];
-        {
-            YPrev lo;
-            // the lower neighbour of y-edge r + 1/2 is y-edge r - 1/2 (yS)
-            g_tilde_r<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE.am, xCurE.t,
-                         xNext.ap, xNext.type, xNextE.am, xNextE.t, G_N);
-            (void)lo;
-        }
+        g_tilde_r<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE.am, xCurE.t,
+                     xNext.ap, xNext.type, xNextE.am, xNextE.t, G_N);
 
         // F(i - 1/2, r): limiter from lanes -1/+1, transverse from the y-edges
         // of columns i-1 (lane - 1) and i (own).
@@ -215,7 +206,7 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 #pragma unroll
         for (int c = 0; c < 3; ++c) F_E[c] = shfl(F_W[c], dn);
 
-        if (core) {
+        if (core && row_ok) {
             double o[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -234,15 +225,15 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
                 if (o[0] < 0.0) { o[0] = 0.0; ++nclamp; }
             }
             if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) ++nbad;
-            size_t k = (size_t)r * P.pitch + i;
+            size_t k = (size_t)(G.base + (long long)r * G.pitch + i);
             P.out0[k] = o[0];
             P.out1[k] = o[1];
             P.out2[k] = o[2];
         }
-        if (xedge_in)
+        if (xedge_in && row_ok)
 #pragma unroll
             for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nux * fabs(xCur.s[p]));
-        if (core)
+        if (core && row_ok)
 #pragma unroll
             for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yN.s[p]));
 
@@ -256,13 +247,143 @@ __global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
 #pragma unroll
         for (int c = 0; c < 3; ++c) G_S[c] = G_N[c];
     }
+}
 
+// Wavefront epilogue: Courant number and counters of the launch.
+__device__ __forceinline__ void march_epilogue(const KParams &P, int lane, double cfl, int nclamp, int nbad)
+{
     cfl = wave_max(cfl);
     unsigned long long mc = __ballot(nclamp > 0), mb = __ballot(nbad > 0);
     if (lane == 0) {
         if (mc && P.n_clamped) atomicAdd(P.n_clamped, __popcll(mc));
         if (mb && P.n_nonfinite) atomicAdd(P.n_nonfinite, __popcll(mb));
         if (P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+    }
+}
+
+template <class M>
+__global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
+{
+    if (!resolve_ctl(P)) return;
+    const int lane = threadIdx.x;
+    const int G = P.nstrips * P.nchunks;
+    const int t = P.xcd_remap ? xcd_logical_block(blockIdx.x, G) : blockIdx.x;
+    const int strip = t / P.nchunks, chunk = t - strip * P.nchunks;
+    const int i = strip * STRIP + lane - HALO;
+    const int j0 = chunk * P.ly;
+    const int j1 = min(j0 + P.ly, P.ny);
+    const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
+    const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
+    double cfl = 0.0;
+    int nclamp = 0, nbad = 0;
+    march<M>(P, uniform_geo(P), lane, i, j0, j1, j1, core, xedge_in, P.dx, P.dy, cfl, nclamp, nbad);
+    march_epilogue(P, lane, cfl, nclamp, nbad);
+}
+
+// ---------------------------------------------------------------------------
+// Batched level: wavefront passes over packed patch strips.
+// ---------------------------------------------------------------------------
+// One pass: each lane decodes its patch and column from the schedule, then the
+// whole wavefront marches `rows` rows (lanes of shorter patches compute the
+// extra rows without storing them; idle lanes load from patch 0 and store
+// nothing).
+template <class M>
+__device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L, int pass, double &cfl,
+                                           int &nclamp, int &nbad)
+{
+    const int lane = threadIdx.x;
+    const long long v = L.lanes[(size_t)pass * WAVE + lane];
+    const bool idle = v < 0;
+    const int patch = idle ? 0 : (int)(v >> 32);
+    const int role = idle ? 0 : (int)((v >> 16) & 0xffff);
+    const int col = idle ? 0 : (int)(v & 0xffff) - 32768;
+    const swe_patch pt = L.patches[patch];
+    Geo G;
+    G.nx = pt.nx; G.ny = pt.ny; G.pitch = pt.nx;
+    G.bc[0] = pt.bc[0]; G.bc[1] = pt.bc[1]; G.bc[2] = pt.bc[2]; G.bc[3] = pt.bc[3];
+    G.base = pt.offset;
+    const int rows = L.pass_rows[pass];
+    march<M>(P, G, lane, col, 0, pt.ny, rows, (role & 1) != 0, (role & 2) != 0, pt.dx, pt.dy, cfl,
+             nclamp, nbad);
+}
+
+// One level step attempt: one wavefront per pass.
+__global__ void __launch_bounds__(WAVE) k_level_step(KParams P, LevelArgs L)
+{
+    if (!resolve_ctl(P)) return;
+    double cfl = 0.0;
+    int nclamp = 0, nbad = 0;
+    level_pass<NL>(P, L, blockIdx.x, cfl, nclamp, nbad);
+    march_epilogue(P, threadIdx.x, cfl, nclamp, nbad);
+}
+
+// Grid barrier of the persistent level kernel (generation counter; the last
+// wavefront to arrive resets the count and opens the next generation).  Each
+// wavefront's Courant-number atomic is complete (s_waitcnt) before it
+// arrives.  A barrier that does not open within a bounded spin raises the
+// error word and lets the wavefront go on, so every wavefront always reaches
+// the end of the kernel.
+__device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nw)
+{
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_s_waitcnt(0);
+        unsigned g = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned arrived = __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nw - 1) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1ll << 22)) {
+                    __hip_atomic_fetch_or(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+    }
+    return __shfl(ok, 0, WAVE) != 0;
+}
+
+// All attempts of a level in one launch: wavefront w does jobs w, w + nw, ...
+// of every attempt; after each attempt the wavefronts meet at the barrier and
+// each applies the control rule to the level's Courant number itself.
+__global__ void __launch_bounds__(WAVE) k_level_persistent(KParams P, LevelArgs L, int n_steps)
+{
+    swe_ctl *c = P.ctl;
+    const unsigned nw = gridDim.x;
+    swe_ctl_state S = c->s;
+    unsigned long long last_bits = 0;
+    bool ran = false;
+    for (int a = 0; a < n_steps && !S.done; ++a) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            __hip_atomic_store(&c->ring[(a + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        KParams Q = P;
+        Q.dt = S.dt;
+        if (S.cur) {
+            Q.in0 = P.out0; Q.in1 = P.out1; Q.in2 = P.out2;
+            Q.out0 = const_cast<double *>(P.in0); Q.out1 = const_cast<double *>(P.in1);
+            Q.out2 = const_cast<double *>(P.in2);
+        }
+        Q.cfl_bits = (unsigned long long *)&c->ring[a % 3];
+        double cfl = 0.0;
+        int nclamp = 0, nbad = 0;
+        for (int j = blockIdx.x; j < L.n_jobs; j += nw)
+            for (int ps = L.job_pass[j]; ps < L.job_pass[j + 1]; ++ps) level_pass<NL>(Q, L, ps, cfl, nclamp, nbad);
+        march_epilogue(Q, threadIdx.x, cfl, nclamp, nbad);
+        if (!level_barrier(L.sync, nw)) break;
+        last_bits = __hip_atomic_load(&c->ring[a % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        S = ctl_apply(S, __longlong_as_double((long long)last_bits), P.cfl_desired, P.cfl_max);
+        ran = true;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c->s = S;
+        if (ran) c->cfl_bits = last_bits;
+        c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
     }
 }
 
@@ -279,7 +400,7 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
     const int up = lane > 0 ? lane - 1 : 0;
     const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
     using Cell = typename M::Cell;
-    Cell c = M::load(P, i, 0);
+    Cell c = M::load(P, uniform_geo(P), i, 0);
     Cell l = M::shfl_cell(c, up);
     Edge x;
     M::solve(l, c, false, P, x);
@@ -515,6 +636,30 @@ hipError_t launch_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_m
 {
     hipLaunchKernelGGL(k_ctl_finish, dim3(1), dim3(1), 0, s, c, n, cfl_desired, cfl_max);
     return hipGetLastError();
+}
+
+hipError_t launch_level_step(const KParams &P, const LevelArgs &L, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_level_step, dim3(L.n_passes), dim3(WAVE), 0, s, P, L);
+    return hipGetLastError();
+}
+
+int level_persistent_capacity()
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_level_persistent, WAVE, 0) != hipSuccess) return 0;
+    return cus * per;
+}
+
+hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s)
+{
+    KParams p = P;
+    LevelArgs l = L;
+    int n = n_steps;
+    void *args[] = {&p, &l, &n};
+    return hipLaunchCooperativeKernel((const void *)k_level_persistent, dim3(nw), dim3(WAVE), args, 0, s);
 }
 
 hipError_t launch_flag(const FlagParams &F, hipStream_t s)

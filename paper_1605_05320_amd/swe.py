@@ -91,7 +91,8 @@ def lib():
                               "(python -m paper_1605_05320_amd.build)")
         L = C.CDLL(LIB_PATH)
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
-                     "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance"):
+                     "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
+                     "swe_level_advance", "swe_level_schedule"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_last_error.restype = C.c_char_p
@@ -251,3 +252,83 @@ def swe_ctl_retarget(ctl, t_out, stream=None):
 def swe_advance(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, stream=None):
     _check(lib().swe_advance(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                              _ptr(ctl), C.c_int32(n_attempts), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# batched AMR level
+# --------------------------------------------------------------------------
+SCHED_STRIP, SCHED_PACKED = 0, 1
+
+
+class swe_patch(C.Structure):
+    _fields_ = [("offset", C.c_int64), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32 * 4),
+                ("dx", C.c_double), ("dy", C.c_double)]
+
+
+class swe_level(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("n_passes", C.c_int32), ("n_jobs", C.c_int32),
+                ("reserved", C.c_int32), ("patches", C.c_void_p), ("lanes", C.c_void_p),
+                ("pass_rows", C.c_void_p), ("job_pass", C.c_void_p), ("sync", C.c_void_p)]
+
+
+def patch_table(nx, ny, dx, dy=None, bc=(BC_WALL,) * 4):
+    """Host array of swe_patch for patches stored back to back (offsets = running sums)."""
+    n = len(nx)
+    tab = (swe_patch * n)()
+    off = 0
+    for k in range(n):
+        tab[k].offset = off
+        tab[k].nx, tab[k].ny = int(nx[k]), int(ny[k])
+        for c in range(4):
+            tab[k].bc[c] = bc[c]
+        tab[k].dx = float(dx[k])
+        tab[k].dy = float(dx[k] if dy is None else dy[k])
+        off += int(nx[k]) * int(ny[k])
+    return tab, off
+
+
+def level_schedule(tab, kind=SCHED_PACKED):
+    """Host schedule: returns (lanes int64[n_passes*64], pass_rows int32[n_passes],
+    job_pass int32[n_jobs+1]) as numpy arrays."""
+    import numpy as np
+    n = len(tab)
+    nj = C.c_int32(0)
+    npass = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind), None, None, None, C.byref(nj))
+    if npass < 0:
+        _check(npass)
+    lanes = np.empty(npass * 64, np.int64)
+    rows = np.empty(npass, np.int32)
+    jp = np.empty(nj.value + 1, np.int32)
+    r = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind),
+                                 lanes.ctypes.data_as(C.c_void_p), rows.ctypes.data_as(C.c_void_p),
+                                 jp.ctypes.data_as(C.c_void_p), C.byref(nj))
+    if r < 0:
+        _check(r)
+    return lanes, rows, jp
+
+
+class Level:
+    """A level's schedule and patch table on the device (tensors kept alive here)."""
+
+    def __init__(self, tab, kind=SCHED_PACKED, device="cuda"):
+        import numpy as np
+        import torch
+        lanes, rows, jp = level_schedule(tab, kind)
+        raw = np.frombuffer(bytes(tab), dtype=np.uint8)
+        self.kind = kind
+        self.patches_t = torch.tensor(raw, dtype=torch.uint8, device=device)
+        self.lanes_t = torch.tensor(lanes, device=device)
+        self.rows_t = torch.tensor(rows, device=device)
+        self.jp_t = torch.tensor(jp, device=device)
+        self.sync_t = torch.zeros(4, dtype=torch.int32, device=device)
+        self.c = swe_level(len(tab), len(rows), len(jp) - 1, 0, self.patches_t.data_ptr(),
+                           self.lanes_t.data_ptr(), self.rows_t.data_ptr(), self.jp_t.data_ptr(),
+                           self.sync_t.data_ptr())
+        self.lane_occupancy = float((lanes >= 0).mean())
+
+
+def level_advance(level: Level, prm: Params, B, a, b, ctl, n_steps: int, persistent: int = 0,
+                  stream=None):
+    _check(lib().swe_level_advance(C.byref(level.c), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
+                                   _ptr(ctl), C.c_int32(n_steps), C.c_int32(persistent),
+                                   _stream(stream)))

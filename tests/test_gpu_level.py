@@ -1,0 +1,109 @@
+"""GPU parity of the batched AMR level (both schedules, per-step and
+persistent launches) against the oracle stepping each patch, with the
+level-wide time step of the device-side control rule (rejection included)."""
+import numpy as np
+import pytest
+
+from paper_1605_05320_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_05320_amd import swe
+    swe.lib()
+    return swe
+
+
+def oracle_level(O, ps, B, q, dt, n_steps, cfl_d=0.9, cfl_max=1.0, t_out=1e30):
+    """Host mirror of the control rule with the Courant number of the level."""
+    p = O.Params(cfl_desired=cfl_d, cfl_max=cfl_max)
+    t, fin, acc, rej = 0.0, False, 0, 0
+    if dt >= t_out - t:
+        dt, fin = t_out - t, True
+    for _ in range(n_steps):
+        new, cfl = [], 0.0
+        for k in range(len(ps.nx)):
+            g = O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k])
+            h, hu, hv, c, _ = O.swe_step(g, p, B[k], *q[k], dt)
+            new.append([h, hu, hv])
+            cfl = max(cfl, c)
+        if cfl > cfl_max:
+            rej += 1
+            dt = dt * cfl_d / cfl
+        else:
+            acc += 1
+            q = new
+            t = t_out if fin else t + dt
+            dt = dt * cfl_d / cfl
+        fin = False
+        if dt >= t_out - t:
+            dt, fin = t_out - t, True
+    return q, t, dt, acc, rej
+
+
+@pytest.fixture(scope="module")
+def setup(oracle):
+    O = oracle
+    ps = I.patches(48, seed=5)
+    ps.nx[0], ps.ny[0] = 64, 37          # a patch of two strips
+    ps.nx[1], ps.ny[1] = 61, 8
+    ps = I.PatchSet(nx=ps.nx, ny=ps.ny, dx=ps.dx, x_lo=ps.x_lo, y_lo=ps.y_lo, B=None, eta0=None)
+    bp = I.basin_params(5)
+    B, q = [], []
+    for k in range(len(ps.nx)):
+        g = I.Grid2D(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k], ps.x_lo[k], ps.y_lo[k])
+        X, Y = g.centres()
+        b = I.bathymetry(X, Y, bp)
+        e = 30.0 * I.source_surface(X, Y, bp) + 0.2 * np.sin(X / 3e3) * np.cos(Y / 4e3)
+        B.append(b)
+        og = O.Grid(g.nx, g.ny, g.dx, g.dy)
+        q.append(O.init_state(og, O.Params(), O.NONLINEAR, b, e))
+    dts = [O.dt0(O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k]), O.Params(), O.NONLINEAR, B[k], *q[k])
+           for k in range(len(ps.nx))]
+    return ps, B, q, min(d for d in dts if d > 0)
+
+
+def to_arena(arrs):
+    return np.concatenate([a.ravel() for a in arrs])
+
+
+@pytest.mark.parametrize("kind,persistent", [(0, 0), (1, 0), (1, 1), (0, 1)])
+def test_level_parity(oracle, S, setup, kind, persistent):
+    ps, B, q, dt0 = setup
+    n_steps = 7
+    qc, t, dt, acc, rej = oracle_level(oracle, ps, B, q, 1.6 * dt0, n_steps)
+    assert rej >= 1 and acc >= 1
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    lvl = S.Level(tab, kind)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    Bd = dev(to_arena(B))
+    a = [dev(to_arena([qq[c] for qq in q])) for c in range(3)]
+    b = [torch.full_like(x, float("nan")) for x in a]
+    ctl = S.new_ctl()
+    S.swe_ctl_set(ctl, 0.0, 1.6 * dt0, 1e30, 0)
+    S.level_advance(lvl, S.Params(), Bd, a, b, ctl, n_steps, persistent)
+    torch.cuda.synchronize()
+    assert int(lvl.sync_t[2].item()) == 0
+    c = S.read_ctl(ctl)
+    assert (c.n_accepted, c.n_rejected, c.t, c.dt) == (acc, rej, t, dt)
+    cur = a if c.cur == 0 else b
+    got = [x.cpu().numpy() for x in cur]
+    off = 0
+    exact = True
+    for k in range(len(ps.nx)):
+        n = int(ps.nx[k]) * int(ps.ny[k])
+        for comp in range(3):
+            g_ = got[comp][off:off + n].reshape(qc[k][comp].shape)
+            r_ = qc[k][comp]
+            if comp == 0:
+                g_, r_ = g_ + B[k], r_ + B[k]
+            scale = np.abs(r_).max() + (1.0 if comp == 0 else 0.0)
+            assert np.abs(g_ - r_).max() <= 1e-12 * max(scale, 1e-300), (k, comp)
+            exact &= np.array_equal(got[comp][off:off + n], qc[k][comp].ravel())
+        off += n
+    print(f"level kind={kind} persistent={persistent}: bit-exact={exact}")
