@@ -242,7 +242,115 @@ def secondary(S, torch, I, np, f64):
     out["step_4096_algorithmic_GBs"] = BYTES_PER_CELL_STEP * n * n / t / 1e9
     del qa, qb, B, e
     torch.cuda.empty_cache()
+    out.update(run_bench(S, torch, I, np, f64))
+    out.update(level_bench(S, torch, I, np, f64))
     return out
+
+
+def run_bench(S, torch, I, np, f64):
+    """The two-phase driver on the adjoint-flagging workload (512^2 basin,
+    64 snapshots, window [3600 s, 7200 s], tol 1e-4, flags every step) and on
+    the 1D shelf (2000 cells, 60 snapshots, 3 h, tol 1e-3)."""
+    out = {}
+    for tag, n, ny, K, ts, tf, tol, model in (("run2d_512", 512, 512, 64, 3600.0, 7200.0, 1e-4, S.NONLINEAR),
+                                              ("run1d_2000", 2000, 1, 60, 0.0, 10800.0, 1e-3, S.LINEAR)):
+        if ny > 1:
+            b = I.basin(n, 3)
+            g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+            Bn, En, target = b.B, b.eta0, b.target
+        else:
+            s1 = I.shelf1d(n, seed=0)
+            g = S.Grid(n, 1, s1.dx, 1.0, s1.x_lo)
+            Bn, En, target = s1.B.reshape(1, n), s1.eta0.reshape(1, n), s1.target
+        ncomp = 3 if ny > 1 else 2
+        prm = S.Params(model=model)
+        B = torch.tensor(Bn, **f64)
+        E = torch.tensor(En, **f64)
+        frames = torch.zeros(K + 1, ncomp, ny, n, **f64)
+        q = [torch.zeros(ny, n, **f64) for _ in range(ncomp)]
+        acc = torch.zeros(ny, n, dtype=torch.int8, device=B.device)
+        macc = torch.zeros(ny, n, **f64)
+        pb = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc)
+        ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
+        S.swe_run(pb, ws)                       # warm-up
+        acc.zero_(); macc.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = S.swe_run(pb, ws)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        cells = n * ny
+        out[tag] = {"s": round(el, 4), "adjoint_steps": r.n_adj_steps, "forward_steps": r.n_fwd_steps,
+                    "flag_passes": r.n_flag_calls, "flagged_cells": int(acc.sum().item()),
+                    "cell_updates_per_s": cells * (r.n_adj_steps + r.n_fwd_steps) / el}
+    return out
+
+
+def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
+    """Batched AMR level: 3000 patches of 8..64 cells a side, 100 steps with a
+    level-wide dt; the autotuned schedule against one launch per patch per step."""
+    ps = I.patches(n_patches, seed=seed)
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    dev = B0 = None
+    B = torch.tensor(np.concatenate([b.ravel() for b in ps.B]), **f64)
+    eta = torch.tensor(np.concatenate([e.ravel() for e in ps.eta0]), **f64)
+    prm = S.Params()
+    init = [torch.empty(ncell, **f64) for _ in range(3)]
+    # initial state and level speed, patch by patch through the library
+    spd = torch.zeros(1, dtype=torch.int64, device=B.device)
+    for k in range(n_patches):
+        o, n = tab[k].offset, tab[k].nx * tab[k].ny
+        g = S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy)
+        q = [x[o:o + n] for x in init]
+        S.swe_init(g, prm, B[o:o + n], eta[o:o + n], q)
+        S.swe_max_speed(g, prm, B[o:o + n], q, 0, spd)
+    dt0 = prm.cfl_desired / float(spd.view(torch.float64).item())
+    levels = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED)]
+    wa = [torch.empty(ncell, **f64) for _ in range(3)]
+    wb = [torch.empty(ncell, **f64) for _ in range(3)]
+    ref = [torch.empty(ncell, **f64) for _ in range(3)]
+    ctl = S.new_ctl()
+    mism = torch.zeros(1, dtype=torch.int32, device=B.device)
+    entries, best = S.level_tune(levels, prm, B, init, wa, wb, ref, ctl, mism, dt0, 10, ncell)
+    names = {(0, 0): "strip/launch-per-step", (0, 1): "strip/persistent",
+             (1, 0): "packed/launch-per-step", (1, 1): "packed/persistent"}
+    lv, pers, _ = entries[best]
+    # timed run of the chosen schedule
+    for c in range(3):
+        wa[c].copy_(init[c])
+    S.swe_ctl_set(ctl, 0.0, dt0, 1.0e300, 0)
+    torch.cuda.synchronize()
+    t = _time_events(torch, lambda: None, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.level_advance(levels[lv], prm, B, wa, wb, ctl, n_steps, pers)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    c = S.read_ctl(ctl)
+    best_rate = ncell * c.n_accepted / (ms * 1e-3)
+    # baseline: one launch per patch per step (fixed dt; no level reduction
+    # round-trip charged to it)
+    views = []
+    for k in range(n_patches):
+        o, n = tab[k].offset, tab[k].nx * tab[k].ny
+        views.append((S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy), B[o:o + n],
+                      [x[o:o + n] for x in wa], [x[o:o + n] for x in wb]))
+    def per_patch_step():
+        for g, bb, qa_, qb_ in views:
+            S.swe_step(g, prm, bb, qa_, qb_, 0.5 * dt0)
+    per_patch = _time_events(torch, per_patch_step, 3)
+    return {"level_patches": n_patches, "level_cells": ncell,
+            "level_candidates_us_per_step": {names[(l, p)]: round(u, 2) for l, p, u in entries},
+            "level_schedule": names[(lv, pers)],
+            "level_lane_occupancy": {"strip": round(levels[0].lane_occupancy, 3),
+                                     "packed": round(levels[1].lane_occupancy, 3)},
+            "level_steps": n_steps, "level_accepted": c.n_accepted,
+            "level_cell_updates_per_s": best_rate,
+            "level_ms_per_step": ms / n_steps,
+            "level_baseline_launch_per_patch_ms_per_step": per_patch * 1e3,
+            "level_baseline_cell_updates_per_s": ncell / per_patch,
+            "level_speedup_vs_launch_per_patch": per_patch * 1e3 / (ms / n_steps)}
 
 
 def cpu_baseline(b, n, budget_s):

@@ -210,6 +210,8 @@ typedef struct {
     swe_ctl_state s;        /* state after the last attempt (valid between swe_advance calls) */
     uint64_t cfl_bits;      /* Courant number of the last attempt */
     int32_t n_clamped, n_nonfinite;
+    int32_t n_flag_calls;   /* flag passes run by swe_advance_flagged */
+    int32_t reserved;
     swe_ctl_state slot[2];  /* kernel-internal: state of the running attempts */
     uint64_t ring[3];       /* kernel-internal: Courant numbers of the running attempts */
 } swe_ctl;
@@ -299,6 +301,52 @@ SWE_API swe_status swe_level_advance(const swe_level *level, const swe_params *p
                                      swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_steps,
                                      int32_t persistent, void *stream);
 
+/* One timed candidate of swe_level_tune. */
+typedef struct {
+    int32_t level;          /* index into the candidate levels */
+    int32_t persistent;
+    double us_per_attempt;
+} swe_tune_entry;
+
+/*
+ * swe_level_tune - autotuner of the batched level: for every candidate level
+ * schedule (levels[k], e.g. SWE_SCHED_STRIP and SWE_SCHED_PACKED of the same
+ * patches) and both launch modes, copy the state `init` into `work_a`, run
+ * n_trial attempts from dt with the control rule, time them with HIP events,
+ * and compare the resulting state bit for bit with the first candidate's (kept
+ * in `ref`).  Writes 2*n_levels entries to `out` (host) and the index of the
+ * fastest into *best.  Returns SWE_E_HIP if two candidates disagree in any
+ * bit (*mismatch, device int32, receives the count).  Synchronises `stream`.
+ */
+SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, const swe_params *prm,
+                                  const double *B, swe_fields init, swe_fields work_a, swe_fields work_b,
+                                  swe_fields ref, swe_ctl *ctl, int32_t *mismatch, double dt,
+                                  int32_t n_trial, int64_t n_cells, swe_tune_entry *out, int32_t *best,
+                                  void *stream);
+
+/* Flagging of a device-controlled forward run (see swe_advance_flagged). */
+typedef struct {
+    const double *frames;   /* (K+1) snapshots, as for adj_flag */
+    int32_t K;
+    int32_t flag_every;     /* >= 1 */
+    double t0, ts, tf, tol;
+    int8_t *flags_final;    /* flags of the attempt that reaches t_out (nullable) */
+    int8_t *flag_acc;       /* OR of all flags (nullable) */
+    double *maxip_acc;      /* max of all m (nullable) */
+} swe_flagging;
+
+/*
+ * swe_advance_flagged - swe_advance with the flag pass of the driver after
+ * every attempt, decided on the device: when the attempt is accepted and
+ * either reaches t_out or brings the accepted-step count (since swe_ctl_set)
+ * to a multiple of flag_every, the new state is flagged at the new time with
+ * the window of adj_window; the flags of the attempt reaching t_out go to
+ * flags_final.  Enqueue only.
+ */
+SWE_API swe_status swe_advance_flagged(const swe_grid *grid, const swe_params *prm, const double *B,
+                                       swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_attempts,
+                                       const swe_flagging *fl, void *stream);
+
 /* Full problem of the two-phase driver. */
 typedef struct {
     swe_grid grid;
@@ -336,9 +384,9 @@ SWE_API size_t swe_run_workspace_bytes(const swe_problem *pb);
  *    { dt = dt0 at first, else dt*cfl_desired/cfl of the previous attempt
  *      (unchanged if cfl = 0), clamped to the next output time t0 + j ds
  *      (the last is tf); step; if cfl > cfl_max the step is discarded and
- *      retried; else accept, and flag when flag_every accepted steps have
- *      passed or an output time was reached (flags at output j stored in
- *      flags_at[j]) } until tf.
+ *      retried; else accept, and flag when an output time was reached (flags
+ *      at output j stored in flags_at[j]) or the number of accepted steps is
+ *      a multiple of flag_every } until tf.
  * Synchronises `stream` (it reads the Courant number of each step) and
  * returns when the run has completed.  workspace: device, at least
  * swe_run_workspace_bytes(pb) bytes, 256-byte aligned.

@@ -1051,8 +1051,9 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
  *      or rejected attempt, unchanged if cfl = 0), clamped to the next output
  *      time t0 + j ds (the last one is tf);
  *      step; if cfl > cfl_max discard and retry with dt cfl_desired/cfl;
- *      otherwise accept and flag if flag_every accepted steps have passed or an
- *      output time was reached (flags at output j are stored);
+ *      otherwise accept, and flag if an output time was reached (flags at
+ *      output j are stored) or the number of accepted steps is a multiple of
+ *      flag_every (every step for flag_every = 1, as in Sec. 4.1);
  *    until tf.
  */
 int or_run(const or_problem *pb, or_result *res)
@@ -1110,7 +1111,6 @@ int or_run(const or_problem *pb, or_result *res)
     double dt = or_dt0(G, P, pb->model, pb->B, a[0], a[1], a[2]);
     if (!(dt > 0.0)) { res->status = -1; goto done; }
     int j = 1;
-    int since = 0;
     while (j <= K) {
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;
         int final = 0;
@@ -1131,14 +1131,11 @@ int or_run(const or_problem *pb, or_result *res)
         res->n_clamped += ncl;
         res->n_fwd_steps++;
         t = final ? tout : t + dt;
-        since++;
         if (final) {
             DO_FLAG(j);
-            since = 0;
             j++;
-        } else if (since == pb->flag_every) {
+        } else if (res->n_fwd_steps % pb->flag_every == 0) {
             DO_FLAG(-1);
-            since = 0;
         }
         if (cfl > 0.0) dt = dt * P->cfl_desired / cfl;
     }

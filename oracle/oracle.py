@@ -104,7 +104,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        src = os.path.join(HERE, "oracle.c")
+        stale = os.path.exists(LIB_PATH) and os.path.exists(src) and \
+            os.path.getmtime(src) > os.path.getmtime(LIB_PATH) and "SWE_ORACLE_LIB" not in os.environ
+        if not os.path.exists(LIB_PATH) or stale:
             build()
         _lib = C.CDLL(LIB_PATH)
         _lib.or_dt0.restype = C.c_double

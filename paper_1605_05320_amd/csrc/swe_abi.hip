@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 
 #include "swe.h"
@@ -283,8 +284,9 @@ swe_status swe_ctl_retarget(swe_ctl *ctl, double t_out, void *stream)
     return SWE_OK;
 }
 
-swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
-                       swe_fields b, swe_ctl *ctl, int32_t n_attempts, void *stream)
+static swe_status advance_impl(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
+                               swe_fields b, swe_ctl *ctl, int32_t n_attempts, const swe_flagging *fl,
+                               void *stream)
 {
     swe_status st;
     if ((st = check_grid(grid)) != SWE_OK) return st;
@@ -299,6 +301,27 @@ swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double
     int model = prm->model == SWE_NONLINEAR ? swe::MODEL_NL : swe::MODEL_LIN;
     if (model == swe::MODEL_NL && grid->ny < 2) return fail(SWE_E_INVAL, "the nonlinear model needs ny >= 2");
     if (model == swe::MODEL_LIN && grid->ny != 1) return fail(SWE_E_INVAL, "the linear model needs ny == 1");
+    swe::FlagParams fp;
+    swe::FlagCtl fc;
+    if (fl) {
+        if (!fl->frames || fl->K < 1 || fl->flag_every < 1 || !(fl->tf > fl->t0))
+            return fail(SWE_E_INVAL, "flagging: need frames, K >= 1, flag_every >= 1, tf > t0");
+        if (!fl->flags_final && !fl->flag_acc && !fl->maxip_acc)
+            return fail(SWE_E_INVAL, "flagging: no output");
+        std::memset(&fp, 0, sizeof fp);
+        fp.nx = grid->nx; fp.ny = grid->ny; fp.pitch = grid->pitch;
+        fp.twod = grid->ny > 1; fp.ncomp = fp.twod ? 3 : 2;
+        fp.nonlinear = prm->model == SWE_NONLINEAR;
+        fp.sea_level = prm->sea_level; fp.dry_tol = prm->dry_tol; fp.tol = fl->tol;
+        fp.B = B; fp.frames = fl->frames;
+        fp.flag_acc = fl->flag_acc; fp.maxip_acc = fl->maxip_acc;
+        std::memset(&fc, 0, sizeof fc);
+        fc.ctl = ctl; fc.K = fl->K; fc.flag_every = fl->flag_every;
+        fc.cfl_desired = prm->cfl_desired; fc.cfl_max = prm->cfl_max;
+        fc.t0 = fl->t0; fc.ts = fl->ts; fc.tf = fl->tf;
+        fc.a0 = a.f0; fc.a1 = a.f1; fc.a2 = a.f2; fc.b0 = b.f0; fc.b1 = b.f1; fc.b2 = b.f2;
+        fc.flags_final = fl->flags_final;
+    }
     swe::KParams k = make_kparams(grid, prm, B, a, b, 1.0, nullptr);
     k.ctl = ctl;
     k.cfl_desired = prm->cfl_desired;
@@ -309,9 +332,27 @@ swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double
     for (int n = 0; n < n_attempts; ++n) {
         k.attempt = n;
         HIP_TRY(swe::launch_step(model, k, s));
+        if (fl) {
+            fc.attempt = n;
+            HIP_TRY(swe::launch_flag_ctl(fp, fc, s));
+        }
     }
     if (n_attempts > 0) HIP_TRY(swe::launch_ctl_finish(ctl, n_attempts, prm->cfl_desired, prm->cfl_max, s));
     return SWE_OK;
+}
+
+swe_status swe_advance(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
+                       swe_fields b, swe_ctl *ctl, int32_t n_attempts, void *stream)
+{
+    return advance_impl(grid, prm, B, a, b, ctl, n_attempts, nullptr, stream);
+}
+
+swe_status swe_advance_flagged(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
+                               swe_fields b, swe_ctl *ctl, int32_t n_attempts, const swe_flagging *fl,
+                               void *stream)
+{
+    if (!fl) return fail(SWE_E_INVAL, "flagging is NULL");
+    return advance_impl(grid, prm, B, a, b, ctl, n_attempts, fl, stream);
 }
 
 swe_status adj_window(double t, double t0, double ts, double tf, int32_t K, int32_t *k_lo, int32_t *k_hi)
@@ -371,6 +412,7 @@ struct Workspace {
     int8_t *flags;
     swe_scalars *sc;
     unsigned long long *speed;
+    swe_ctl *ctl;
     size_t bytes;
 };
 
@@ -414,6 +456,8 @@ static size_t ws_layout(const swe_problem *pb, Workspace *w, char *base)
     off = align256(off + sizeof(swe_scalars));
     if (w) w->speed = (unsigned long long *)(base + off);
     off = align256(off + sizeof(unsigned long long));
+    if (w) w->ctl = (swe_ctl *)(base + off);
+    off = align256(off + sizeof(swe_ctl));
     if (w) w->bytes = off;
     return off;
 }
@@ -492,66 +536,61 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         }
     }
 
-    // ---- phase B: forward with flagging
+    // ---- phase B: forward with flagging, stepped and flagged on the device;
+    // the host only waits once per output segment
     swe_fields cur = A, nxt = Bf;
     if ((st = swe_init(G, P, pb->B, pb->eta0, cur, stream)) != SWE_OK) return st;
-    double t = pb->t0;
-    auto do_flag = [&](int store_idx) -> swe_status {
+    {
         int32_t lo, hi;
-        swe_status s2 = adj_window(t, pb->t0, pb->ts, pb->tf, K, &lo, &hi);
-        if (s2 != SWE_OK) return s2;
-        int8_t *fl = store_idx >= 0 && pb->flags_at ? pb->flags_at + (size_t)store_idx * plane : w.flags;
-        s2 = adj_flag(G, P, pb->B, cur, pb->frames, K, lo, hi, pb->tol, fl, nullptr, pb->flag_acc,
-                      pb->maxip_acc, stream);
-        res->n_flag_calls++;
-        return s2;
-    };
-    if ((st = do_flag(0)) != SWE_OK) return st;
+        if ((st = adj_window(pb->t0, pb->t0, pb->ts, pb->tf, K, &lo, &hi)) != SWE_OK) return st;
+        int8_t *fl0 = pb->flags_at ? pb->flags_at : w.flags;
+        if ((st = adj_flag(G, P, pb->B, cur, pb->frames, K, lo, hi, pb->tol, fl0, nullptr, pb->flag_acc,
+                           pb->maxip_acc, stream)) != SWE_OK)
+            return st;
+    }
     HIP_TRY(hipMemsetAsync(w.speed, 0, sizeof(unsigned long long), s));
     if ((st = swe_max_speed(G, P, pb->B, cur, 0, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
     HIP_TRY(hipMemcpyAsync(&spb, w.speed, sizeof spb, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     smax = bits_to_double(spb);
     if (!(smax > 0.0)) return fail(SWE_E_INVAL, "no wet cell for the forward problem");
-    double dt = P->cfl_desired / smax;
-    int j = 1, since = 0, rejected = 0;
-    swe_scalars hs;
-    while (j <= K) {
+    double dt0 = P->cfl_desired / smax;
+    swe_flagging fl;
+    fl.frames = pb->frames;
+    fl.K = K;
+    fl.flag_every = pb->flag_every;
+    fl.t0 = pb->t0; fl.ts = pb->ts; fl.tf = pb->tf; fl.tol = pb->tol;
+    fl.flag_acc = pb->flag_acc;
+    fl.maxip_acc = pb->maxip_acc;
+    swe_ctl hc;
+    for (int j = 1; j <= K; ++j) {
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;
-        bool fin = false;
-        if (dt >= tout - t) {
-            dt = tout - t;
-            fin = true;
+        if (j == 1) {
+            if ((st = swe_ctl_set(w.ctl, pb->t0, dt0, tout, 0, stream)) != SWE_OK) return st;
+        } else {
+            if ((st = swe_ctl_retarget(w.ctl, tout, stream)) != SWE_OK) return st;
         }
-        HIP_TRY(hipMemsetAsync(w.sc, 0, sizeof(swe_scalars), s));
-        if ((st = swe_step(G, P, pb->B, cur, nxt, dt, w.sc, stream)) != SWE_OK) return st;
-        HIP_TRY(hipMemcpyAsync(&hs, w.sc, sizeof hs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        double cfl = bits_to_double(hs.cfl_bits);
-        if (hs.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state at t = %g", t);
-        if (cfl > P->cfl_max) {
-            res->n_rejected++;
-            if (++rejected > 1000) return fail(SWE_E_CFL, "no acceptable step at t = %g", t);
-            dt = dt * P->cfl_desired / cfl;
-            continue;
+        fl.flags_final = pb->flags_at ? pb->flags_at + (size_t)j * plane : w.flags;
+        int rounds = 0;
+        while (!hc.s.done) {
+            double need = std::ceil((tout - hc.s.t) / hc.s.dt);
+            int n = (int)std::min(std::max(need, 0.0) + 2.0, 100000.0);
+            if ((st = swe_advance_flagged(G, P, pb->B, A, Bf, w.ctl, n, &fl, stream)) != SWE_OK) return st;
+            HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hc.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state near t = %g", hc.s.t);
+            if (++rounds > 1000 || hc.s.n_rejected > 1000) return fail(SWE_E_CFL, "no progress at t = %g", hc.s.t);
         }
-        swe_fields tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        res->n_clamped += hs.n_clamped;
-        res->n_fwd_steps++;
-        t = fin ? tout : t + dt;
-        ++since;
-        if (fin) {
-            if ((st = do_flag(j)) != SWE_OK) return st;
-            since = 0;
-            ++j;
-        } else if (since == pb->flag_every) {
-            if ((st = do_flag(-1)) != SWE_OK) return st;
-            since = 0;
-        }
-        if (cfl > 0.0) dt = dt * P->cfl_desired / cfl;
     }
+    cur = hc.s.cur ? Bf : A;
+    (void)nxt;
+    res->n_fwd_steps = hc.s.n_accepted;
+    res->n_rejected = hc.s.n_rejected;
+    res->n_clamped = hc.n_clamped;
+    res->n_flag_calls = 1 + hc.n_flag_calls;
+    double t = hc.s.t;
     // final state into q_out
     size_t row_bytes = (size_t)G->nx * sizeof(double), pitch_bytes = (size_t)G->pitch * sizeof(double);
     double *dst[3] = {pb->q_out.f0, pb->q_out.f1, pb->q_out.f2};

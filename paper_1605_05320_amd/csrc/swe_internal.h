@@ -24,6 +24,15 @@ struct FlagParams {
     double *maxip_acc;
 };
 
+// Device-side flag scheduling after a controlled step attempt.
+struct FlagCtl {
+    swe_ctl *ctl;
+    int attempt, K, flag_every;
+    double cfl_desired, cfl_max, t0, ts, tf;
+    const double *a0, *a1, *a2, *b0, *b1, *b2;
+    int8_t *flags_final;
+};
+
 struct CellParams {
     int nx, ny, pitch;
     double dx, dy, x_lo, y_lo;
@@ -37,9 +46,11 @@ swe_status fail(swe_status st, const char *fmt, ...);
 
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s);
 hipError_t launch_level_step(const KParams &P, const LevelArgs &L, hipStream_t s);
 hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s);
 int level_persistent_capacity();
+hipError_t launch_count_diff(const double *a, const double *b, long long n, int *out, hipStream_t s);
 hipError_t launch_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur, hipStream_t s);
 hipError_t launch_ctl_retarget(swe_ctl *c, double t_out, hipStream_t s);
 hipError_t launch_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max, hipStream_t s);

@@ -456,6 +456,7 @@ __global__ void k_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur
     c->cfl_bits = 0;
     c->n_clamped = 0;
     c->n_nonfinite = 0;
+    c->n_flag_calls = 0;
     c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
 }
 
@@ -511,6 +512,81 @@ __global__ void __launch_bounds__(256) k_flag(FlagParams F)
         int8_t fl = m > F.tol ? 1 : 0;
         if (F.flags) F.flags[k] = fl;
         if (F.maxip) F.maxip[k] = m;
+        if (F.flag_acc) F.flag_acc[k] = (int8_t)(F.flag_acc[k] | fl);
+        if (F.maxip_acc) F.maxip_acc[k] = dmax(F.maxip_acc[k], m);
+    }
+}
+
+// Window of eq. (ip_timerange) on the device (same arithmetic as adj_window).
+__device__ __forceinline__ double dev_snap(double r)
+{
+    double rr = rint(r);
+    return fabs(r - rr) <= 1e-9 ? rr : r;
+}
+
+__device__ __forceinline__ bool dev_window(double t, double t0, double ts, double tf, int K, int &lo, int &hi)
+{
+    double ds = (tf - t0) / K;
+    double T = fmin(t + (tf - ts), tf);
+    double sa = tf - T, sb = tf - t;
+    if (sb < 0.0) {
+        lo = 1;
+        hi = 0;
+        return false;
+    }
+    double l = floor(dev_snap(sa / ds)), h = ceil(dev_snap(sb / ds));
+    if (l < 0.0) l = 0.0;
+    if (h > K) h = K;
+    lo = (int)l;
+    hi = (int)h;
+    return true;
+}
+
+// Flagging after step attempt `attempt` of a device-controlled sequence: the
+// attempt's outcome is derived from its state slot and its (now complete)
+// Courant number; if it was accepted and either reached the segment's output
+// time or its accepted-step count is a multiple of flag_every, flag the new
+// state (in plane set a or b according to the new cur) at the new time.
+__global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
+{
+    swe_ctl *c = C.ctl;
+    swe_ctl_state S = ctl_apply(c->slot[C.attempt & 1],
+                                __longlong_as_double((long long)c->ring[C.attempt % 3]), C.cfl_desired, C.cfl_max);
+    if (!S.last_accepted) return;
+    if (!(S.done || S.n_accepted % C.flag_every == 0)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) c->n_flag_calls = c->n_flag_calls + 1;
+    int lo, hi;
+    dev_window(S.t, C.t0, C.ts, C.tf, C.K, lo, hi);
+    F.k_lo = lo;
+    F.k_hi = hi;
+    if (S.cur) { F.q0 = C.b0; F.q1 = C.b1; F.q2 = C.b2; }
+    else       { F.q0 = C.a0; F.q1 = C.a1; F.q2 = C.a2; }
+    F.flags = S.done ? C.flags_final : nullptr;
+    const long long n = (long long)F.nx * F.ny;
+    const size_t plane = (size_t)F.ny * F.pitch;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
+        size_t k = (size_t)j * F.pitch + i;
+        double B = F.B[k];
+        double hb = dmax(0.0, F.sea_level - B);
+        bool adj_wet = hb > F.dry_tol;
+        double q0 = F.q0[k];
+        bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
+        double m = 0.0;
+        if (adj_wet && fwd_wet) {
+            double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
+            double q1 = F.q1[k];
+            double q2 = F.twod ? F.q2[k] : 0.0;
+            const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
+            for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
+                double ip = eta * fr[0] + q1 * fr[plane];
+                if (F.twod) ip = ip + q2 * fr[2 * plane];
+                m = dmax(m, fabs(ip));
+            }
+        }
+        int8_t fl = m > F.tol ? 1 : 0;
+        if (F.flags) F.flags[k] = fl;
         if (F.flag_acc) F.flag_acc[k] = (int8_t)(F.flag_acc[k] | fl);
         if (F.maxip_acc) F.maxip_acc[k] = dmax(F.maxip_acc[k], m);
     }
@@ -660,6 +736,29 @@ hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_s
     int n = n_steps;
     void *args[] = {&p, &l, &n};
     return hipLaunchCooperativeKernel((const void *)k_level_persistent, dim3(nw), dim3(WAVE), args, 0, s);
+}
+
+// Count elements whose bit patterns differ (schedule-invariance checks).
+__global__ void __launch_bounds__(256) k_count_diff(const double *a, const double *b, long long n, int *out)
+{
+    int local = 0;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+         k += (long long)gridDim.x * blockDim.x)
+        local += __double_as_longlong(a[k]) != __double_as_longlong(b[k]);
+    for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && local) atomicAdd(out, local);
+}
+
+hipError_t launch_count_diff(const double *a, const double *b, long long n, int *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_diff, dim3(grid_cells(n)), dim3(256), 0, s, a, b, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flag_ctl, dim3(grid_cells((long long)F.nx * F.ny)), dim3(256), 0, s, F, C);
+    return hipGetLastError();
 }
 
 hipError_t launch_flag(const FlagParams &F, hipStream_t s)

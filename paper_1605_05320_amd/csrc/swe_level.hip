@@ -200,4 +200,85 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
     return SWE_OK;
 }
 
+swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, const swe_params *prm, const double *B,
+                          swe_fields init, swe_fields work_a, swe_fields work_b, swe_fields ref, swe_ctl *ctl,
+                          int32_t *mismatch, double dt, int32_t n_trial, int64_t n_cells, swe_tune_entry *out,
+                          int32_t *best, void *stream)
+{
+    using swe::fail;
+    if (!levels || n_levels < 1 || !prm || !B || !ctl || !mismatch || !out || !best)
+        return fail(SWE_E_INVAL, "null argument");
+    if (!(dt > 0.0) || n_trial < 1 || n_cells < 1) return fail(SWE_E_INVAL, "need dt > 0, n_trial >= 1, n_cells >= 1");
+    if (!init.f0 || !init.f1 || !init.f2 || !ref.f0 || !ref.f1 || !ref.f2) return fail(SWE_E_INVAL, "null plane");
+    hipStream_t s = (hipStream_t)stream;
+    size_t bytes = (size_t)n_cells * sizeof(double);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(SWE_E_HIP, "event creation failed");
+    }
+#define TUNE_HIP(expr)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(SWE_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+    double best_us = 1e300;
+    int nout = 0;
+    bool have_ref = false;
+    auto run_candidate = [&](int k, int pers) -> swe_status {
+        swe_status st;
+        const double *src[3] = {init.f0, init.f1, init.f2};
+        double *dst[3] = {work_a.f0, work_a.f1, work_a.f2};
+        for (int c = 0; c < 3; ++c) TUNE_HIP(hipMemcpyAsync(dst[c], src[c], bytes, hipMemcpyDeviceToDevice, s));
+        if ((st = swe_ctl_set(ctl, 0.0, dt, 1.0e300, 0, stream)) != SWE_OK) return st;
+        TUNE_HIP(hipEventRecord(e0, s));
+        if ((st = swe_level_advance(levels[k], prm, B, work_a, work_b, ctl, n_trial, pers, stream)) != SWE_OK)
+            return st;
+        TUNE_HIP(hipEventRecord(e1, s));
+        TUNE_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        TUNE_HIP(hipEventElapsedTime(&ms, e0, e1));
+        swe_ctl hc;
+        uint32_t syncw[4] = {0, 0, 0, 0};
+        TUNE_HIP(hipMemcpy(&hc, ctl, sizeof hc, hipMemcpyDeviceToHost));
+        if (levels[k]->sync) TUNE_HIP(hipMemcpy(syncw, levels[k]->sync, sizeof syncw, hipMemcpyDeviceToHost));
+        if (syncw[2]) return fail(SWE_E_HIP, "persistent level barrier timed out");
+        swe_fields cur = hc.s.cur ? work_b : work_a;
+        double *cp[3] = {cur.f0, cur.f1, cur.f2};
+        double *rp[3] = {ref.f0, ref.f1, ref.f2};
+        if (!have_ref) {
+            for (int c = 0; c < 3; ++c) TUNE_HIP(hipMemcpyAsync(rp[c], cp[c], bytes, hipMemcpyDeviceToDevice, s));
+            TUNE_HIP(hipStreamSynchronize(s));
+            have_ref = true;
+        } else {
+            TUNE_HIP(hipMemsetAsync(mismatch, 0, sizeof(int32_t), s));
+            for (int c = 0; c < 3; ++c) TUNE_HIP(swe::launch_count_diff(cp[c], rp[c], n_cells, mismatch, s));
+            int32_t hm = 0;
+            TUNE_HIP(hipMemcpyAsync(&hm, mismatch, sizeof hm, hipMemcpyDeviceToHost, s));
+            TUNE_HIP(hipStreamSynchronize(s));
+            if (hm != 0)
+                return fail(SWE_E_HIP, "schedule %d (persistent %d) differs from the first in %d values", k, pers, hm);
+        }
+        double us = ms * 1e3 / n_trial;
+        out[nout].level = k;
+        out[nout].persistent = pers;
+        out[nout].us_per_attempt = us;
+        if (us < best_us) {
+            best_us = us;
+            *best = nout;
+        }
+        ++nout;
+        return SWE_OK;
+    };
+#undef TUNE_HIP
+    swe_status st = SWE_OK;
+    for (int k = 0; k < n_levels && st == SWE_OK; ++k)
+        for (int pers = 0; pers < 2 && st == SWE_OK; ++pers) st = run_candidate(k, pers);
+    hipError_t es = hipStreamSynchronize(s);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == SWE_OK && es != hipSuccess) st = fail(SWE_E_HIP, "synchronisation failed: %s", hipGetErrorString(es));
+    return st;
+}
+
 } // extern "C"

@@ -66,7 +66,8 @@ class swe_ctl_state(C.Structure):
 
 class swe_ctl(C.Structure):
     _fields_ = [("s", swe_ctl_state), ("cfl_bits", C.c_uint64), ("n_clamped", C.c_int32),
-                ("n_nonfinite", C.c_int32), ("slot", swe_ctl_state * 2), ("ring", C.c_uint64 * 3)]
+                ("n_nonfinite", C.c_int32), ("n_flag_calls", C.c_int32), ("reserved", C.c_int32),
+                ("slot", swe_ctl_state * 2), ("ring", C.c_uint64 * 3)]
 
     # flat access to the resolved state
     def __getattr__(self, name):
@@ -92,7 +93,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
-                     "swe_level_advance", "swe_level_schedule"):
+                     "swe_level_advance", "swe_level_schedule", "swe_level_tune"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_last_error.restype = C.c_char_p
@@ -332,3 +333,21 @@ def level_advance(level: Level, prm: Params, B, a, b, ctl, n_steps: int, persist
     _check(lib().swe_level_advance(C.byref(level.c), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                                    _ptr(ctl), C.c_int32(n_steps), C.c_int32(persistent),
                                    _stream(stream)))
+
+
+class swe_tune_entry(C.Structure):
+    _fields_ = [("level", C.c_int32), ("persistent", C.c_int32), ("us_per_attempt", C.c_double)]
+
+
+def level_tune(levels, prm: Params, B, init, work_a, work_b, ref, ctl, mismatch, dt, n_trial, n_cells,
+               stream=None):
+    """Autotune the level schedule (see swe_level_tune).  Returns (entries, best)."""
+    n = len(levels)
+    arr = (C.POINTER(swe_level) * n)(*[C.pointer(l.c) for l in levels])
+    out = (swe_tune_entry * (2 * n))()
+    best = C.c_int32(-1)
+    _check(lib().swe_level_tune(arr, C.c_int32(n), C.byref(prm.c()), _ptr(B), fields(init),
+                                fields(work_a), fields(work_b), fields(ref), _ptr(ctl), _ptr(mismatch),
+                                C.c_double(dt), C.c_int32(n_trial), C.c_int64(n_cells), out,
+                                C.byref(best), _stream(stream)))
+    return [(e.level, e.persistent, e.us_per_attempt) for e in out], best.value

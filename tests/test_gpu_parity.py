@@ -307,14 +307,15 @@ def test_run_1d_parity(oracle, S):
     assert rc.flag_acc.any()
 
 
-def test_run_2d_parity(oracle, S):
+@pytest.mark.parametrize("flag_every,ts", [(1, 3600.0), (3, 0.0)])
+def test_run_2d_parity(oracle, S, flag_every, ts):
     O = oracle
     n = 96
     b = I.basin(n, 3)
     go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
     rc, res, frames, q, flags_at, acc, macc = _run_pair(O, S, go, gs, O.NONLINEAR, b.B, b.eta0,
                                                          (b.target[0], b.target[1], 60e3),
-                                                         0.0, 3600.0, 7200.0, 16, 1e-4)
+                                                         0.0, ts, 7200.0, 16, 1e-4, flag_every=flag_every)
     assert res.n_sub == rc.n_sub and res.n_fwd_steps == rc.n_fwd_steps and res.t_end == rc.t_end
     assert res.n_flag_calls == rc.n_flag_calls
     assert close(frames, rc.frames)
