@@ -64,6 +64,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph", type=int, default=100,
                     help="attempts per captured HIP graph (0: plain stream launches)")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests in the serving trace (grids --serve-nmin..--serve-nmax a side)")
+    ap.add_argument("--serve-nmin", type=int, default=256)
+    ap.add_argument("--serve-nmax", type=int, default=1024)
+    ap.add_argument("--serve-full", action="store_true",
+                    help="the full serving workload: 256 requests, grids 256^2..2048^2")
+    ap.add_argument("--serve-only", action="store_true", help="run the serving leg only (no headline)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -82,6 +89,12 @@ def main():
     S.lib()
     dev = torch.device("cuda")
     f64 = dict(dtype=torch.float64, device=dev)
+    if args.serve_full:
+        args.serve_requests, args.serve_nmin, args.serve_nmax = 256, 256, 2048
+    if args.serve_only:
+        print(json.dumps({"serve": serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin,
+                                               args.serve_nmax)}), flush=True)
+        return
 
     n = args.n
     b = I.basin(n, args.seed)
@@ -151,6 +164,7 @@ def main():
              "wall_s": round(t_wall, 4), "graph_chunk": chunk}
     if not args.no_extra:
         extra.update(secondary(S, torch, I, np, f64))
+        extra["serve"] = serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin, args.serve_nmax)
 
     if args.copy_probe:
         # one copy of known size, for scaling the HBM counters
@@ -351,6 +365,79 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
             "level_baseline_launch_per_patch_ms_per_step": per_patch * 1e3,
             "level_baseline_cell_updates_per_s": ncell / per_patch,
             "level_speedup_vs_launch_per_patch": per_patch * 1e3 / (ms / n_steps)}
+
+
+def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, tol=1e-4, flag_every=4,
+                max_active=8, load=1.5, seed=17):
+    """Serving: scenarios (basin seed 1000 + k, grid n ~ U{nmin..nmax} a side,
+    32 adjoint snapshots, forward to 2 h with flagging) through swe_serve.
+
+    1. sequential plain solves (one scenario at a time, all queued at t = 0)
+       give the service rate mu;
+    2. offline capacity of the served loop (max_active in flight);
+    3. a Poisson trace at lambda = load * mu, replayed in real time through
+       the sequential solver and through the served loop: p50/p99 latency
+       (arrival to results on the host) and scenarios/s.
+    Each served result is compared bit for bit with its sequential one."""
+    trace = I.arrivals(n_req, 1.0, nmin, nmax, seed=seed)
+    reqs = []
+    for a in trace:
+        b = I.basin(a.n, a.seed)
+        g = S.Grid(a.n, a.n, b.grid.dx, b.grid.dy)
+        reqs.append(S.Request(g, S.Params(), b.B, b.eta0, b.target, 0.0, ts, tf, K, tol,
+                              flag_every=flag_every))
+    foot = [S.serve_footprint(r) for r in reqs]
+    free, _ = torch.cuda.mem_get_info()
+    arena_bytes = int(min(0.8 * free, max(foot) * max_active * 1.25, 200 * 2**30))
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    S.serve(reqs[:1], arena, 1)                         # warm-up (code objects, first launches)
+
+    def run(active, realtime):
+        t = time.perf_counter()
+        _, st = S.serve(reqs, arena, active, realtime=realtime)
+        return time.perf_counter() - t, st
+
+    el_seq, st_seq = run(1, False)
+    ref = [(r.flag_acc.copy(), r.maxip_acc.copy(), [q.copy() for q in r.q]) for r in reqs]
+    mu = n_req / el_seq
+    el_cap, st_cap = run(max_active, False)
+
+    def same():
+        return all(np.array_equal(r.flag_acc, f) and np.array_equal(r.maxip_acc, m)
+                   and all(np.array_equal(x, y) for x, y in zip(r.q, qs))
+                   for r, (f, m, qs) in zip(reqs, ref))
+
+    ok_cap = same()
+    lam = load * mu
+    for r, a in zip(reqs, trace):
+        r.c.arrival = a.arrival / lam                   # rate-1 exponential gaps scaled to lambda
+    el_rt_seq, st_rt_seq = run(1, True)
+    el_rt, st_rt = run(max_active, True)
+    ok_rt = same()
+
+    def lat(st):
+        x = np.array([s["latency"] for s in st])
+        return {"p50_s": round(float(np.percentile(x, 50)), 4), "p99_s": round(float(np.percentile(x, 99)), 4),
+                "mean_s": round(float(x.mean()), 4)}
+
+    span = lambda st: max(s["finished"] for s in st) - min(r.c.arrival for r in reqs)
+    cells = [a.n * a.n for a in trace]
+    steps = [s["n_adj_steps"] + s["n_fwd_steps"] for s in st_seq]
+    return {
+        "requests": n_req, "grid_side": [nmin, nmax], "snapshots": K, "t_final_s": tf, "window_start_s": ts,
+        "tol": tol, "flag_every": flag_every, "max_active": max_active,
+        "arena_GiB": round(arena_bytes / 2**30, 2), "footprint_GiB_max": round(max(foot) / 2**30, 3),
+        "cell_updates_total": int(sum(c * s for c, s in zip(cells, steps))),
+        "sequential_scen_per_s": round(mu, 3),
+        "served_offline_scen_per_s": round(n_req / el_cap, 3),
+        "served_offline_speedup": round(el_seq / el_cap, 3),
+        "served_offline_cell_updates_per_s": sum(c * s for c, s in zip(cells, steps)) / el_cap,
+        "poisson_rate_per_s": round(lam, 3), "load_vs_sequential": load,
+        "sequential_realtime": dict(lat(st_rt_seq), scen_per_s=round(n_req / span(st_rt_seq), 3)),
+        "served_realtime": dict(lat(st_rt), scen_per_s=round(n_req / span(st_rt), 3)),
+        "p99_speedup": round(lat(st_rt_seq)["p99_s"] / max(lat(st_rt)["p99_s"], 1e-9), 3),
+        "results_identical_to_sequential": bool(ok_cap and ok_rt),
+    }
 
 
 def cpu_baseline(b, n, budget_s):

@@ -347,6 +347,61 @@ SWE_API swe_status swe_advance_flagged(const swe_grid *grid, const swe_params *p
                                        swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_attempts,
                                        const swe_flagging *fl, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: scenarios (a tsunami source on a grid, with its target region and
+ * time window) arriving over time, run through the two-phase driver with
+ * several in flight at once.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double arrival;             /* seconds after the start of swe_serve */
+    swe_grid grid;              /* pitch must equal nx */
+    swe_params params;
+    const double *B_host;       /* host, ny*nx: bottom elevation */
+    const double *eta0_host;    /* host, ny*nx: initial surface */
+    double target_xc, target_yc, target_R;
+    int32_t target_shape, K;
+    double t0, ts, tf, tol;
+    int32_t flag_every, reserved;
+    int8_t *flag_acc_host;      /* host outputs, ny*nx each (nullable) */
+    double *maxip_acc_host;
+    double *q_host[3];          /* final state planes (nullable) */
+} swe_request;
+
+typedef struct {
+    double admitted;            /* seconds after the start: memory and a slot granted */
+    double finished;            /* results copied back */
+    double latency;             /* finished - arrival (finished when not realtime) */
+    int32_t status;             /* swe_status of the run */
+    int32_t slot;               /* worker that ran it */
+    int32_t n_adj_steps, n_fwd_steps;
+    size_t bytes;               /* device footprint */
+} swe_request_stats;
+
+typedef struct {
+    void *arena;                /* device memory scenarios are carved from (256-byte aligned) */
+    size_t arena_bytes;
+    int32_t max_active;         /* scenarios in flight, one stream and host thread each (>= 1) */
+    int32_t realtime;           /* 1: a request is not admitted before its arrival time */
+} swe_serve_config;
+
+/* Device bytes one request occupies while it runs (0 on bad input). */
+SWE_API size_t swe_serve_footprint(const swe_request *req);
+
+/*
+ * swe_serve - continuous serving of n requests (in order of arrival).
+ * Requests are admitted first-come first-served as soon as (realtime) they
+ * have arrived, a slot is free and their footprint fits in the arena (first
+ * fit); each admitted request copies its inputs to the device, runs swe_run
+ * on its slot's stream while other requests run on theirs, copies its outputs
+ * back and frees its memory, which admits the next ones.  max_active = 1 gives
+ * the plain sequential solver.  A request whose footprint exceeds the arena is
+ * refused (status SWE_E_NOMEM) without blocking the others.  Blocks until all
+ * requests are done; per-request timing in stats.  Returns the first failing
+ * request's status, else SWE_OK.
+ */
+SWE_API swe_status swe_serve(const swe_request *req, int32_t n, const swe_serve_config *cfg,
+                             swe_request_stats *stats);
+
 /* Full problem of the two-phase driver. */
 typedef struct {
     swe_grid grid;

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe.so")
-SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip"]
+SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip", "swe_serve.hip"]
 
 # binary64 without contraction (results are defined op by op); packed FP32
 # instructions disabled.
@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

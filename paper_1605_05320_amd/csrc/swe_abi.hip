@@ -42,14 +42,13 @@ using swe::fail;
 // 2 resident wavefronts per SIMD (register-limited).
 int wave_slots()
 {
-    static int slots = 0;
-    if (slots == 0) {
+    static const int slots = [] {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        slots = cus * 4 * 2;
-    }
+        return cus * 4 * 2;
+    }();
     return slots;
 }
 
@@ -59,12 +58,11 @@ int wave_slots()
 // SWE_MARCH_ROWS overrides it (tuning sweeps).
 int default_ly(int nx, int ny)
 {
-    static int forced = -1;
-    if (forced < 0) {
+    static const int forced = [] {
         const char *e = std::getenv("SWE_MARCH_ROWS");
         int v = e ? std::atoi(e) : 0;
-        forced = (v >= 1 && v <= 4096) ? v : 0;
-    }
+        return (v >= 1 && v <= 4096) ? v : 0;
+    }();
     if (forced > 0) return forced;
     long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
     for (int ly = 8; ly <= 32; ++ly)
@@ -78,11 +76,10 @@ int default_ly(int nx, int ny)
 // SWE_XCD_REMAP=0/1 forces it.
 int xcd_remap_for(int nx, int ny, int ly)
 {
-    static int forced = -2;
-    if (forced == -2) {
+    static const int forced = [] {
         const char *e = std::getenv("SWE_XCD_REMAP");
-        forced = e ? (std::atoi(e) != 0) : -1;
-    }
+        return e ? (std::atoi(e) != 0 ? 1 : 0) : -1;
+    }();
     if (forced >= 0) return forced;
     long long waves = (long long)((nx + swe::STRIP - 1) / swe::STRIP) * ((ny + ly - 1) / ly);
     return waves <= wave_slots() ? 1 : 0;

@@ -93,9 +93,11 @@ def lib():
         L = C.CDLL(LIB_PATH)
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
-                     "swe_level_advance", "swe_level_schedule", "swe_level_tune"):
+                     "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
+                     "swe_serve"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
+        L.swe_serve_footprint.restype = C.c_size_t
         L.swe_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -253,6 +255,97 @@ def swe_ctl_retarget(ctl, t_out, stream=None):
 def swe_advance(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, stream=None):
     _check(lib().swe_advance(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                              _ptr(ctl), C.c_int32(n_attempts), _stream(stream)))
+
+
+class swe_flagging(C.Structure):
+    _fields_ = [("frames", C.c_void_p), ("K", C.c_int32), ("flag_every", C.c_int32),
+                ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
+                ("flags_final", C.c_void_p), ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p)]
+
+
+def swe_advance_flagged(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, frames, K, flag_every,
+                        t0, ts, tf, tol, flags_final=None, flag_acc=None, maxip_acc=None, stream=None):
+    fl = swe_flagging(frames.data_ptr(), K, flag_every, t0, ts, tf, tol,
+                      None if flags_final is None else flags_final.data_ptr(),
+                      None if flag_acc is None else flag_acc.data_ptr(),
+                      None if maxip_acc is None else maxip_acc.data_ptr())
+    _check(lib().swe_advance_flagged(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
+                                     _ptr(ctl), C.c_int32(n_attempts), C.byref(fl), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+class swe_request(C.Structure):
+    _fields_ = [("arrival", C.c_double), ("grid", swe_grid), ("params", swe_params),
+                ("B_host", C.c_void_p), ("eta0_host", C.c_void_p),
+                ("target_xc", C.c_double), ("target_yc", C.c_double), ("target_R", C.c_double),
+                ("target_shape", C.c_int32), ("K", C.c_int32),
+                ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
+                ("flag_every", C.c_int32), ("reserved", C.c_int32),
+                ("flag_acc_host", C.c_void_p), ("maxip_acc_host", C.c_void_p), ("q_host", C.c_void_p * 3)]
+
+
+class swe_request_stats(C.Structure):
+    _fields_ = [("admitted", C.c_double), ("finished", C.c_double), ("latency", C.c_double),
+                ("status", C.c_int32), ("slot", C.c_int32), ("n_adj_steps", C.c_int32),
+                ("n_fwd_steps", C.c_int32), ("bytes", C.c_size_t)]
+
+
+class swe_serve_config(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_active", C.c_int32),
+                ("realtime", C.c_int32)]
+
+
+class Request:
+    """One scenario for swe_serve, with host input and output arrays (numpy,
+    C-contiguous float64 / int8 of shape (ny, nx)) kept alive here."""
+
+    def __init__(self, grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, flag_every=1,
+                 shape=GAUSS, arrival=0.0, want_q=True):
+        import numpy as np
+        self.B = np.ascontiguousarray(B, dtype=np.float64)
+        self.eta0 = np.ascontiguousarray(eta0, dtype=np.float64)
+        shp = self.B.shape
+        ncomp = 3 if grid.ny > 1 else 2
+        self.flag_acc = np.zeros(shp, np.int8)
+        self.maxip_acc = np.zeros(shp, np.float64)
+        self.q = [np.zeros(shp, np.float64) for _ in range(ncomp)] if want_q else []
+        r = swe_request()
+        r.arrival = arrival
+        r.grid = grid.c()
+        r.params = prm.c()
+        r.B_host = self.B.ctypes.data
+        r.eta0_host = self.eta0.ctypes.data
+        r.target_xc, r.target_yc, r.target_R = target
+        r.target_shape, r.K = shape, K
+        r.t0, r.ts, r.tf, r.tol = t0, ts, tf, tol
+        r.flag_every = flag_every
+        r.flag_acc_host = self.flag_acc.ctypes.data
+        r.maxip_acc_host = self.maxip_acc.ctypes.data
+        for c in range(3):
+            r.q_host[c] = self.q[c].ctypes.data if c < len(self.q) else None
+        self.c = r
+
+
+def serve_footprint(req: Request) -> int:
+    return lib().swe_serve_footprint(C.byref(req.c))
+
+
+def serve(reqs, arena, max_active: int, realtime: bool = False, check: bool = True):
+    """Run swe_serve over a list of Request (ordered by arrival) with the
+    device tensor ``arena`` as memory.  Returns (status, list of stats dicts)."""
+    n = len(reqs)
+    arr = (swe_request * n)(*[r.c for r in reqs])
+    st = (swe_request_stats * n)()
+    cfg = swe_serve_config(arena.data_ptr(), arena.numel() * arena.element_size(), max_active,
+                           1 if realtime else 0)
+    rc = lib().swe_serve(arr, C.c_int32(n), C.byref(cfg), st)
+    if check:
+        _check(rc)
+    out = [dict(admitted=s.admitted, finished=s.finished, latency=s.latency, status=s.status, slot=s.slot,
+                n_adj_steps=s.n_adj_steps, n_fwd_steps=s.n_fwd_steps, bytes=s.bytes) for s in st]
+    return rc, out
 
 
 # --------------------------------------------------------------------------

@@ -1,0 +1,120 @@
+"""Serving through swe_serve: a scenario's results are identical whether it
+runs alone or in a mix with others in flight; they match the oracle's run;
+admission never exceeds the arena or the slot count; a request larger than
+the arena is refused without blocking the rest; and realtime admission waits
+for each arrival."""
+import numpy as np
+import pytest
+
+from paper_1605_05320_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL = 1e-12
+K, T0, TS, TF, TOL, FLAG_EVERY, R_TARGET = 8, 0.0, 1800.0, 3600.0, 1e-4, 2, 60e3
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_05320_amd import swe
+    swe.lib()
+    return swe
+
+
+def make_request(S, n, seed, arrival=0.0):
+    b = I.basin(n, seed)
+    g = S.Grid(b.grid.nx, b.grid.ny, b.grid.dx, b.grid.dy, b.grid.x_lo, b.grid.y_lo)
+    target = (b.target[0], b.target[1], R_TARGET)
+    print(f"request n={n} seed={seed} arrival={arrival:.3f}", flush=True)
+    return S.Request(g, S.Params(), b.B, b.eta0, target, T0, TS, TF, K, TOL, flag_every=FLAG_EVERY,
+                     arrival=arrival), b
+
+
+def outputs(r):
+    return [r.flag_acc.copy(), r.maxip_acc.copy()] + [q.copy() for q in r.q]
+
+
+def arena_for(S, reqs, copies=1):
+    nbytes = max(S.serve_footprint(r) for r in reqs) * copies
+    return torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+
+def trace(S, n_req=8, nmin=48, nmax=128):
+    return [make_request(S, a.n, a.seed)[0] for a in I.arrivals(n_req, 50.0, nmin, nmax, seed=5)]
+
+
+def test_mix_equals_alone(S):
+    reqs = trace(S)
+    alone = []
+    for r in reqs:
+        arena = arena_for(S, [r])
+        _, st = S.serve([r], arena, 1)
+        assert st[0]["status"] == 0
+        alone.append((outputs(r), st[0]))
+        r.flag_acc[:] = 0
+        r.maxip_acc[:] = 0
+        for q in r.q:
+            q[:] = 0
+    arena = arena_for(S, reqs, copies=4)
+    _, st = S.serve(reqs, arena, 4)
+    slots = {s["slot"] for s in st}
+    assert len(slots) > 1, "the mix never ran two scenarios at once"
+    for r, s, (ref, s1) in zip(reqs, st, alone):
+        assert s["status"] == 0
+        assert s["n_fwd_steps"] == s1["n_fwd_steps"] and s["n_adj_steps"] == s1["n_adj_steps"]
+        for x, y in zip(outputs(r), ref):
+            assert np.array_equal(x, y)
+    assert any(r.flag_acc.any() for r in reqs)
+
+
+def test_served_matches_oracle(oracle, S):
+    O = oracle
+    for n, seed in [(64, 1001), (77, 1002)]:
+        r, b = make_request(S, n, seed)
+        arena = arena_for(S, [r])
+        _, st = S.serve([r], arena, 1)
+        go = O.Grid(n, n, b.grid.dx, b.grid.dy, b.grid.x_lo, b.grid.y_lo, (0, 0, 0, 0))
+        rc = O.run(go, O.Params(), O.NONLINEAR, b.B, b.eta0, (b.target[0], b.target[1], R_TARGET),
+                   T0, TS, TF, K, TOL, flag_every=FLAG_EVERY)
+        assert st[0]["n_fwd_steps"] == rc.n_fwd_steps and st[0]["n_adj_steps"] == rc.n_adj_steps
+        eta_g, eta_c = r.q[0] + b.B, rc.q[0] + b.B
+        assert np.abs(eta_g - eta_c).max() <= REL * (np.abs(eta_c).max() + 1.0)
+        for c in (1, 2):
+            assert np.abs(r.q[c] - rc.q[c]).max() <= REL * np.abs(rc.q[c]).max()
+        assert np.abs(r.maxip_acc - rc.maxip_acc).max() <= REL * np.abs(rc.maxip_acc).max()
+        band = np.abs(rc.maxip_acc - TOL) <= 1e-12 * TOL
+        assert np.array_equal(r.flag_acc[~band], rc.flag_acc[~band])
+        print(f"served {n}: bit-exact={all(np.array_equal(x, y) for x, y in zip(r.q, rc.q))}")
+
+
+def test_admission_respects_arena_and_slots(S):
+    reqs = trace(S, n_req=6, nmin=96, nmax=128)
+    big, _ = make_request(S, 200, 77)
+    reqs.insert(3, big)
+    arena = arena_for(S, reqs[:3] + reqs[4:], copies=2)
+    cap = arena.numel()
+    assert S.serve_footprint(big) > cap
+    rc, st = S.serve(reqs, arena, 3, check=False)
+    assert rc == S.E_NOMEM
+    assert st[3]["status"] == S.E_NOMEM and st[3]["slot"] == -1
+    for k, s in enumerate(st):
+        if k != 3:
+            assert s["status"] == 0 and s["slot"] >= 0
+    events = sorted({s["admitted"] for k, s in enumerate(st) if k != 3})
+    for t in events:
+        live = [s for k, s in enumerate(st) if k != 3 and s["admitted"] <= t < s["finished"]]
+        assert sum(s["bytes"] for s in live) <= cap
+        assert len(live) <= 3
+
+
+def test_realtime_admission_waits_for_arrival(S):
+    reqs = [make_request(S, 64, 1000 + k, arrival=0.15 * k)[0] for k in range(4)]
+    arena = arena_for(S, reqs, copies=4)
+    _, st = S.serve(reqs, arena, 4, realtime=True)
+    for r, s in zip(reqs, st):
+        assert s["status"] == 0
+        assert s["admitted"] >= r.c.arrival
+        assert abs(s["latency"] - (s["finished"] - r.c.arrival)) < 1e-9
