@@ -73,10 +73,10 @@ __device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const 
         double cx[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int p = 0; p < M::NW; ++p) {
-            const bool from_lo = e.s[p] > 0.0;
+            const bool upwind_lo = e.s[p] > 0.0;
             double uz[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) uz[c] = from_lo ? lo.z[p][c] : hi.z[p][c];
+            for (int c = 0; c < 3; ++c) uz[c] = upwind_lo ? lo.z[p][c] : hi.z[p][c];
             double dd, du;
             if (M::zc(p, 0) && M::zc(p, 1)) {
                 dd = e.z[p][0] * e.z[p][0] + e.z[p][1] * e.z[p][1];
@@ -122,9 +122,6 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
 {
     const double nux = P.dt / dx, nuy = P.dt / dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
-    const int up = lane > 0 ? lane - 1 : 0;
-    const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
-
     using Cell = typename M::Cell;
     QRow qC;                 // row r (being updated)
     Cell cD;                 // row r + 1
@@ -132,27 +129,29 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     Edge yN, xCur;           // y-edge r + 1/2, x-edge of row r
     XFl xCurE;               // its east neighbour's A-dQ
     double G_S[3];           // G of edge r - 1/2
+    RawCell rE;              // stored values of row r + 2, loaded one row ahead
     {
         Cell cA = M::load(P, G, i, j0 - 2);
         Cell cB = M::load(P, G, i, j0 - 1);
         Cell cC = M::load(P, G, i, j0);
         cD = M::load(P, G, i, j0 + 1);
+        rE = M::raw(P, G, i, j0 + 2);
         Edge yS2, yS0, xPrev;
         M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
         M::solve(cB, cC, true, P, yS0);            // y-edge j0 - 1/2
         M::solve(cC, cD, true, P, yN);             // y-edge j0 + 1/2
-        Cell lB = M::shfl_cell(cB, up);
+        Cell lB = M::lo_cell(cB);
         M::solve(lB, cB, false, P, xPrev);         // x-edge (i - 1/2, j0 - 1)
-        Cell lC = M::shfl_cell(cC, up);
+        Cell lC = M::lo_cell(cC);
         M::solve(lC, cC, false, P, xCur);          // x-edge (i - 1/2, j0)
         XFl ePrev;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            ePrev.am[c] = shfl(xPrev.am[c], dn);
-            xCurE.am[c] = shfl(xCur.am[c], dn);
+            ePrev.am[c] = from_hi(xPrev.am[c]);
+            xCurE.am[c] = from_hi(xCur.am[c]);
         }
-        ePrev.t = shfl(xPrev.type, dn);
-        xCurE.t = shfl(xCur.type, dn);
+        ePrev.t = from_hi(xPrev.type);
+        xCurE.t = from_hi(xCur.type);
         YPrev lo2;
         keep_yprev<M>(yS2, lo2);
         g_tilde_r<M>(yS0, lo2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
@@ -166,15 +165,16 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
 
     for (int r = j0; r < jend; ++r) {
         const bool row_ok = r < j1;
-        Cell cE = M::load(P, G, i, r + 2);
+        Cell cE = M::cell(P, rE);
+        rE = M::raw(P, G, i, r + 3);               // in flight during this row
         Edge yNN, xNext;
         M::solve(cD, cE, true, P, yNN);            // y-edge r + 3/2
-        Cell lD = M::shfl_cell(cD, up);
+        Cell lD = M::lo_cell(cD);
         M::solve(lD, cD, false, P, xNext);         // x-edge (i - 1/2, r + 1)
         XFl xNextE;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) xNextE.am[c] = shfl(xNext.am[c], dn);
-        xNextE.t = shfl(xNext.type, dn);
+        for (int c = 0; c < 3; ++c) xNextE.am[c] = from_hi(xNext.am[c]);
+        xNextE.t = from_hi(xNext.type);
 
         // G(i, r + 1/2); the lower neighbour of y-edge r + 1/2 is y-edge r - 1/2
         double G_N[3];
@@ -186,14 +186,14 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         double F_W[3] = {0.0, 0.0, 0.0};
         {
             double Fn[3] = {0.0, 0.0, 0.0};
-            if (P.order == 2) correction_lanes<M>(xCur, nux, lane, Fn);
+            if (P.order == 2) correction_lanes<M>(xCur, nux, Fn);
             double yS_ap_W[3], yN_am_W[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                yS_ap_W[c] = shfl(yS.ap[c], up);
-                yN_am_W[c] = shfl(yN.am[c], up);
+                yS_ap_W[c] = from_lo(yS.ap[c]);
+                yN_am_W[c] = from_lo(yN.am[c]);
             }
-            int yS_t_W = shfl(yS.type, up), yN_t_W = shfl(yN.type, up);
+            int yS_t_W = from_lo(yS.type), yN_t_W = from_lo(yN.type);
             if (xCur.type == E_WET) {
                 to_phys(false, Fn, F_W);
                 if (P.transverse)
@@ -204,7 +204,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         }
         double F_E[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) F_E[c] = shfl(F_W[c], dn);
+        for (int c = 0; c < 3; ++c) F_E[c] = from_hi(F_W[c]);
 
         if (core && row_ok) {
             double o[3];
@@ -262,7 +262,7 @@ __device__ __forceinline__ void march_epilogue(const KParams &P, int lane, doubl
 }
 
 template <class M>
-__global__ void __launch_bounds__(WAVE) k_march2d(KParams P)
+__global__ void __launch_bounds__(WAVE, 2) k_march2d(KParams P)
 {
     if (!resolve_ctl(P)) return;
     const int lane = threadIdx.x;
@@ -308,7 +308,7 @@ __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L,
 }
 
 // One level step attempt: one wavefront per pass.
-__global__ void __launch_bounds__(WAVE) k_level_step(KParams P, LevelArgs L)
+__global__ void __launch_bounds__(WAVE, 2) k_level_step(KParams P, LevelArgs L)
 {
     if (!resolve_ctl(P)) return;
     double cfl = 0.0;
@@ -352,7 +352,7 @@ __device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nw)
 // All attempts of a level in one launch: wavefront w does jobs w, w + nw, ...
 // of every attempt; after each attempt the wavefronts meet at the barrier and
 // each applies the control rule to the level's Courant number itself.
-__global__ void __launch_bounds__(WAVE) k_level_persistent(KParams P, LevelArgs L, int n_steps)
+__global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelArgs L, int n_steps)
 {
     swe_ctl *c = P.ctl;
     const unsigned nw = gridDim.x;
@@ -397,22 +397,20 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
     const double nu = P.dt / P.dx;
     const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
     const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
-    const int up = lane > 0 ? lane - 1 : 0;
-    const int dn = lane < WAVE - 1 ? lane + 1 : WAVE - 1;
     using Cell = typename M::Cell;
     Cell c = M::load(P, uniform_geo(P), i, 0);
-    Cell l = M::shfl_cell(c, up);
+    Cell l = M::lo_cell(c);
     Edge x;
     M::solve(l, c, false, P, x);
     double F[3] = {0.0, 0.0, 0.0};
     if (P.order == 2) {
         double Fn[3] = {0.0, 0.0, 0.0};
-        correction_lanes<M>(x, nu, lane, Fn);
+        correction_lanes<M>(x, nu, Fn);
         if (x.type == E_WET) to_phys(false, Fn, F);
     }
     double FE[3], amE[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { FE[k] = shfl(F[k], dn); amE[k] = shfl(x.am[k], dn); }
+    for (int k = 0; k < 3; ++k) { FE[k] = from_hi(F[k]); amE[k] = from_hi(x.am[k]); }
     if (core) {
         double o[2];
 #pragma unroll
