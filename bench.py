@@ -38,6 +38,51 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+COPY_PROBE_BYTES = 64 * 1024 * 1024 * 8    # the --copy-probe copy: 512 MiB read and written
+STEP_KERNEL = "k_march2d<swe::NL"
+
+
+def _counter_rows(d: str, counter: str):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    return rows
+
+
+def traffic_from(fetch_dir: str, write_dir: str, n: int):
+    """HBM bytes per step-kernel launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for the 512 MiB
+    device copy of --copy-probe."""
+    out = {"kernel": "k_march2d<NL> (order 2, transverse)", "kernel_source_sha": kernel_source_hash(),
+           "workload": f"{n}x{n} synthetic basin, seed 2", "copy_probe_bytes": COPY_PROBE_BYTES}
+    for kind, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _counter_rows(d, kind.upper() + "_SIZE")
+        step = [float(r["Counter_Value"]) for r in rows if STEP_KERNEL in r["Kernel_Name"]]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower()]
+        probe = max(copies, key=lambda r: int(r["Grid_Size"]))
+        probe_kib = float(probe["Counter_Value"])
+        scale = COPY_PROBE_BYTES / 1024.0 / probe_kib
+        out[f"{kind}_kib_per_launch"] = sum(step) / len(step)
+        out[f"{kind}_launches"] = len(step)
+        out[f"{kind}_copy_probe_kib"] = probe_kib
+        out[f"{kind}_scale"] = scale
+        out[f"{kind}_bytes_per_launch"] = sum(step) / len(step) * 1024.0 * scale
+    out["hbm_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    out["algorithmic_bytes_per_launch"] = BYTES_PER_CELL_STEP * n * n
+    out["traffic_over_algorithmic"] = out["hbm_bytes_per_launch"] / out["algorithmic_bytes_per_launch"]
+    path = os.path.join(ROOT, "profiles", "step_nl_1024_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
 def load_traffic(kind: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
@@ -73,7 +118,14 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only (no headline)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of known size (HBM counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: read two rocprofv3 --pmc outputs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --graph 0 --copy-probe' and write the step kernel's HBM traffic "
+                         "to profiles/step_nl_1024_traffic.json")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from, n=args.n)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "the grid and scenario decompositions across GPUs are described, not run.",
@@ -350,10 +402,21 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
         o, n = tab[k].offset, tab[k].nx * tab[k].ny
         views.append((S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy), B[o:o + n],
                       [x[o:o + n] for x in wa], [x[o:o + n] for x in wb]))
-    def per_patch_step():
+    def per_patch_step(stream=None):
         for g, bb, qa_, qb_ in views:
-            S.swe_step(g, prm, bb, qa_, qb_, 0.5 * dt0)
-    per_patch = _time_events(torch, per_patch_step, 3)
+            S.swe_step(g, prm, bb, qa_, qb_, 0.5 * dt0, stream=stream)
+    per_patch_eager = _time_events(torch, per_patch_step, 2)
+    # the fair baseline: the 3000 launches of one step captured once in a HIP
+    # graph and replayed (no host cost per launch)
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cs):
+        with torch.cuda.graph(graph, stream=cs):
+            per_patch_step(stream=cs)
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    per_patch = _time_events(torch, graph.replay, 5)
     return {"level_patches": n_patches, "level_cells": ncell,
             "level_candidates_us_per_step": {names[(l, p)]: round(u, 2) for l, p, u in entries},
             "level_schedule": names[(lv, pers)],
@@ -363,6 +426,7 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
             "level_cell_updates_per_s": best_rate,
             "level_ms_per_step": ms / n_steps,
             "level_baseline_launch_per_patch_ms_per_step": per_patch * 1e3,
+            "level_baseline_launch_per_patch_eager_ms_per_step": per_patch_eager * 1e3,
             "level_baseline_cell_updates_per_s": ncell / per_patch,
             "level_speedup_vs_launch_per_patch": per_patch * 1e3 / (ms / n_steps)}
 

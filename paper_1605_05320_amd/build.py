@@ -1,6 +1,7 @@
 """Build the HIP library ``libswe.so`` (gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -9,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe.so")
+STAMP = LIB + ".sources"      # hash of the sources the library was built from
 SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip", "swe_serve.hip"]
 
 # binary64 without contraction (results are defined op by op); packed FP32
@@ -16,6 +18,18 @@ SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip", "swe_serve.hip"]
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-ffp-contract=off",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+
+
+def sources_hash() -> str:
+    """sha256 over the library's sources and headers."""
+    h = hashlib.sha256()
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for f in names:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    with open(os.path.join(ROOT, "include", "swe.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
 
 
 def build(verbose: bool = False) -> str:
@@ -35,6 +49,8 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    with open(STAMP, "w") as f:
+        f.write(sources_hash() + "\n")
     return LIB
 
 

@@ -13,7 +13,8 @@ import os
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("SWE_LIB") or os.path.join(HERE, "libswe.so")
+DEFAULT_LIB = os.path.join(HERE, "libswe.so")
+LIB_PATH = os.environ.get("SWE_LIB") or DEFAULT_LIB
 
 OK, E_INVAL, E_CFL, E_HIP, E_NOMEM, E_NONFINITE, E_NEGDEPTH = 0, -1, -2, -3, -4, -5, -6
 BC_WALL, BC_EXTRAP = 0, 1
@@ -90,6 +91,17 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
                               "(python -m paper_1605_05320_amd.build)")
+        if LIB_PATH == DEFAULT_LIB:
+            # refuse a library built from other sources than those in the tree
+            from . import build as _build
+            try:
+                with open(_build.STAMP) as f:
+                    stamp = f.read().strip()
+            except OSError:
+                stamp = ""
+            if stamp != _build.sources_hash():
+                raise ImportError(f"{LIB_PATH} was not built from the current sources: rebuild it "
+                                  "(python -m paper_1605_05320_amd.build)")
         L = C.CDLL(LIB_PATH)
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
