@@ -336,9 +336,18 @@ def run_bench(S, torch, I, np, f64):
         q = [torch.zeros(ny, n, **f64) for _ in range(ncomp)]
         acc = torch.zeros(ny, n, dtype=torch.int8, device=B.device)
         macc = torch.zeros(ny, n, **f64)
+        # warm-up, recording the adjoint flags and the surface flags (|eta| >
+        # surface_tol) at t0 and the K output times for comparison
+        flags_at = torch.zeros(K + 1, ny, n, dtype=torch.int8, device=B.device)
+        sflags = torch.zeros(K + 1, ny, n, dtype=torch.int8, device=B.device)
+        stol = 0.05 if ny > 1 else 0.02
+        pw = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, flags_at, acc, macc,
+                            surface_tol=stol, surface_flags_at=sflags)
+        ws = torch.empty(S.swe_run_workspace_bytes(pw) // 8 + 64, **f64)
+        S.swe_run(pw, ws)
+        adj_counts = flags_at.view(K + 1, -1).sum(dim=1, dtype=torch.int64).cpu().tolist()
+        srf_counts = sflags.view(K + 1, -1).sum(dim=1, dtype=torch.int64).cpu().tolist()
         pb = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc)
-        ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
-        S.swe_run(pb, ws)                       # warm-up
         acc.zero_(); macc.zero_()
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -348,7 +357,11 @@ def run_bench(S, torch, I, np, f64):
         cells = n * ny
         out[tag] = {"s": round(el, 4), "adjoint_steps": r.n_adj_steps, "forward_steps": r.n_fwd_steps,
                     "flag_passes": r.n_flag_calls, "flagged_cells": int(acc.sum().item()),
-                    "cell_updates_per_s": cells * (r.n_adj_steps + r.n_fwd_steps) / el}
+                    "cell_updates_per_s": cells * (r.n_adj_steps + r.n_fwd_steps) / el,
+                    "flagged_per_output": {"adjoint_tol": tol, "surface_tol_m": stol,
+                                           "adjoint": adj_counts, "surface": srf_counts,
+                                           "adjoint_mean": sum(adj_counts) / len(adj_counts),
+                                           "surface_mean": sum(srf_counts) / len(srf_counts)}}
     return out
 
 

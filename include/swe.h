@@ -324,6 +324,19 @@ SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_leve
                                   int32_t n_trial, int64_t n_cells, swe_tune_entry *out, int32_t *best,
                                   void *stream);
 
+/*
+ * swe_surface_flag - the surface criterion the adjoint flagging is compared
+ * with (Sec. 7: refine where the sea surface relative to sea level exceeds a
+ * tolerance): flags[k] = 1 if cell k is wet and |eta| > tol, else 0, with
+ * eta = (h + B) - sea_level and wet = h > dry_tol for the nonlinear model, and
+ * eta = q.f0, wet = max(0, sea_level - B) > dry_tol for the linear model.
+ * flags (nullable) and flag_acc (nullable, |= flag) are device int8 planes
+ * with the grid's pitch.  Enqueue only.  SWE_E_INVAL: bad grid, null B or
+ * q.f0, no output, non-finite tol.
+ */
+SWE_API swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                                    double tol, int8_t *flags, int8_t *flag_acc, void *stream);
+
 /* Flagging of a device-controlled forward run (see swe_advance_flagged). */
 typedef struct {
     const double *frames;   /* (K+1) snapshots, as for adj_flag */
@@ -420,6 +433,9 @@ typedef struct {
     int8_t *flags_at;       /* device, (K+1)*ny*pitch: flags at t0 + j ds; nullable */
     int8_t *flag_acc;       /* device plane, OR of all flags (caller zeroes); nullable */
     double *maxip_acc;      /* device plane, max of all m (caller zeroes); nullable */
+    double surface_tol;     /* tolerance of the surface criterion (with surface_flags_at) */
+    int8_t *surface_flags_at; /* device, (K+1)*ny*pitch: swe_surface_flag at t0 + j ds, for
+                                 comparison with flags_at; nullable */
 } swe_problem;
 
 typedef struct {

@@ -1039,6 +1039,34 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
     }
 }
 
+/*
+ * Surface flagging, the default refinement criterion the adjoint method is
+ * compared with (Sec. 7): a cell is flagged when the sea surface relative to
+ * sea level exceeds the tolerance, read here as |eta| > tol (a trough counts
+ * as a wave as much as a crest), in cells that are wet.  eta = (h + B) -
+ * sea_level, wet = h > dry_tol (nonlinear); eta = first component, wet =
+ * adjoint-wet (linear).  flag_acc (if non-null) |= flag.
+ */
+void or_surface_flag(const or_grid *G, const or_params *P, int model, const double *B,
+                     const double *q0, double tol, signed char *flags, signed char *flag_acc)
+{
+    size_t n = (size_t)G->nx * G->ny;
+    for (size_t k = 0; k < n; k++) {
+        int wet;
+        double eta;
+        if (model == OR_NONLINEAR) {
+            wet = q0[k] > P->dry_tol;
+            eta = (q0[k] + B[k]) - P->sea_level;
+        } else {
+            wet = MAXD(0.0, P->sea_level - B[k]) > P->dry_tol;
+            eta = q0[k];
+        }
+        signed char fl = (wet && fabs(eta) > tol) ? 1 : 0;
+        if (flags) flags[k] = fl;
+        if (flag_acc) flag_acc[k] = (signed char)(flag_acc[k] | fl);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* driver                                                                   */
 /* ------------------------------------------------------------------------ */
@@ -1046,7 +1074,8 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
  * Two-phase run (Sec. 4):
  * A. adjoint: q~(0) = phi, advanced with constant dt = ds/n_sub; frame k
  *    (k = 0..K) is q~ at reversed time k ds, i.e. q^(tau = tf - k ds).
- * B. forward from t0 with the initial state of eta0: flag at t0, then repeat
+ * B. forward from t0 with the initial state of eta0: flag at t0 (and, if
+ *    asked, surface-flag at t0 and at every output time), then repeat
  *      choose dt (initially dt0, then dt cfl_desired/cfl of the last accepted
  *      or rejected attempt, unchanged if cfl = 0), clamped to the next output
  *      time t0 + j ds (the last one is tf);
@@ -1105,6 +1134,9 @@ int or_run(const or_problem *pb, or_result *res)
         or_flag(G, P, pb->model, pb->B, a[0], a[1], a[2], pb->frames, K, klo, khi, pb->tol, \
                 fl, NULL, pb->flag_acc, pb->maxip_acc); \
         if ((store_idx) >= 0 && pb->flags_at) memcpy(pb->flags_at + (size_t)(store_idx) * n, fl, n); \
+        if ((store_idx) >= 0 && pb->surface_flags_at) \
+            or_surface_flag(G, P, pb->model, pb->B, a[0], pb->surface_tol, \
+                            pb->surface_flags_at + (size_t)(store_idx) * n, NULL); \
         res->n_flag_calls++; } while (0)
 
     DO_FLAG(0);

@@ -43,6 +43,8 @@ typedef struct {
     signed char *flags_at;  /* (K+1) * nx * ny, nullable */
     signed char *flag_acc;  /* nullable */
     double *maxip_acc;      /* nullable */
+    double surface_tol;             /* tolerance of the surface criterion */
+    signed char *surface_flags_at;  /* (K+1) * nx * ny surface flags at t0 and the output times, nullable */
 } or_problem;
 
 typedef struct {
@@ -73,6 +75,8 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
              const double *q0, const double *q1, const double *q2,
              const double *frames, int K, int k_lo, int k_hi, double tol,
              signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc);
+void or_surface_flag(const or_grid *G, const or_params *P, int model, const double *B,
+                     const double *q0, double tol, signed char *flags, signed char *flag_acc);
 int or_run(const or_problem *pb, or_result *res);
 
 #ifdef __cplusplus

@@ -57,7 +57,8 @@ class _Problem(C.Structure):
                 ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
                 ("K", C.c_int), ("flag_every", C.c_int),
                 ("frames", _dp), ("q_out", _dp * 3),
-                ("flags_at", _bp), ("flag_acc", _bp), ("maxip_acc", _dp)]
+                ("flags_at", _bp), ("flag_acc", _bp), ("maxip_acc", _dp),
+                ("surface_tol", C.c_double), ("surface_flags_at", _bp)]
 
 
 class _Result(C.Structure):
@@ -245,12 +246,24 @@ class RunResult:
     status: int
     dt_adj: float
     t_end: float
+    surface_flags_at: np.ndarray = None
     extra: dict = field(default_factory=dict)
 
 
+def surface_flag(grid: Grid, prm: Params, model, B, q0, tol, flag_acc=None):
+    """Surface flags |eta| > tol in wet cells (the criterion of Sec. 7)."""
+    shp = (grid.ny, grid.nx)
+    B, q0 = _f64(B, shp), _f64(q0, shp)
+    fl = np.zeros(shp, np.int8)
+    lib().or_surface_flag(C.byref(grid.c()), C.byref(prm.c()), C.c_int(model), _p(B), _p(q0),
+                          C.c_double(tol), _b(fl), _b(flag_acc) if flag_acc is not None else None)
+    return fl
+
+
 def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
-        flag_every=1, target_shape=GAUSS) -> RunResult:
-    """Adjoint snapshots then the forward run with flagging (Sec. 4)."""
+        flag_every=1, target_shape=GAUSS, surface_tol=None) -> RunResult:
+    """Adjoint snapshots then the forward run with flagging (Sec. 4); with
+    surface_tol, also the surface flags at t0 and at the output times."""
     shp = (grid.ny, grid.nx)
     n = grid.nx * grid.ny
     ncomp = 3 if grid.ny > 1 else 2
@@ -273,6 +286,10 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
     for c in range(3):
         pb.q_out[c] = _p(q[c])
     pb.flags_at, pb.flag_acc, pb.maxip_acc = _b(flags_at), _b(acc), _p(macc)
+    sflags = None
+    if surface_tol is not None:
+        sflags = np.zeros((K + 1,) + shp, np.int8)
+        pb.surface_tol, pb.surface_flags_at = surface_tol, _b(sflags)
     res = _Result()
     lib().or_run(C.byref(pb), C.byref(res))
     del n
@@ -280,4 +297,4 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
                      n_adj_steps=res.n_adj_steps, n_sub=res.n_sub, n_fwd_steps=res.n_fwd_steps,
                      n_rejected=res.n_rejected, n_flag_calls=res.n_flag_calls,
                      n_clamped=res.n_clamped, status=res.status, dt_adj=res.dt_adj,
-                     t_end=res.t_end)
+                     t_end=res.t_end, surface_flags_at=sflags)

@@ -401,6 +401,21 @@ swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B
     return SWE_OK;
 }
 
+swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q, double tol,
+                            int8_t *flags, int8_t *flag_acc, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if ((st = check_params(prm)) != SWE_OK) return st;
+    if (!B || !q.f0) return fail(SWE_E_INVAL, "B or q.f0 is NULL");
+    if (!flags && !flag_acc) return fail(SWE_E_INVAL, "no output requested");
+    if (!std::isfinite(tol)) return fail(SWE_E_INVAL, "tol must be finite");
+    swe_fields none = {nullptr, nullptr, nullptr};
+    HIP_TRY(swe::launch_surface_flag(make_cparams(grid, prm, B, none), q.f0, tol, prm->model == SWE_NONLINEAR,
+                                     flags, flag_acc, (hipStream_t)stream));
+    return SWE_OK;
+}
+
 // ---------------------------------------------------------------------------
 // two-phase driver
 // ---------------------------------------------------------------------------
@@ -544,6 +559,10 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         if ((st = adj_flag(G, P, pb->B, cur, pb->frames, K, lo, hi, pb->tol, fl0, nullptr, pb->flag_acc,
                            pb->maxip_acc, stream)) != SWE_OK)
             return st;
+        if (pb->surface_flags_at &&
+            (st = swe_surface_flag(G, P, pb->B, cur, pb->surface_tol, pb->surface_flags_at, nullptr, stream)) !=
+                SWE_OK)
+            return st;
     }
     HIP_TRY(hipMemsetAsync(w.speed, 0, sizeof(unsigned long long), s));
     if ((st = swe_max_speed(G, P, pb->B, cur, 0, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
@@ -579,6 +598,12 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
             HIP_TRY(hipStreamSynchronize(s));
             if (hc.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state near t = %g", hc.s.t);
             if (++rounds > 1000 || hc.s.n_rejected > 1000) return fail(SWE_E_CFL, "no progress at t = %g", hc.s.t);
+        }
+        if (pb->surface_flags_at) {
+            swe_fields now = hc.s.cur ? Bf : A;
+            if ((st = swe_surface_flag(G, P, pb->B, now, pb->surface_tol, pb->surface_flags_at + (size_t)j * plane,
+                                       nullptr, stream)) != SWE_OK)
+                return st;
         }
     }
     cur = hc.s.cur ? Bf : A;

@@ -46,6 +46,8 @@ swe_status fail(swe_status st, const char *fmt, ...);
 
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_surface_flag(const CellParams &C, const double *q0, double tol, int nonlinear, int8_t *flags,
+                               int8_t *flag_acc, hipStream_t s);
 hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s);
 hipError_t launch_level_step(const KParams &P, const LevelArgs &L, hipStream_t s);
 hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s);

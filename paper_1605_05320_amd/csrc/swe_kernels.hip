@@ -633,6 +633,31 @@ __global__ void __launch_bounds__(256) k_init(CellParams C, const double *eta0, 
     }
 }
 
+// Surface criterion: flag = wet && |eta| > tol, eta relative to sea level.
+__global__ void __launch_bounds__(256) k_surface_flag(CellParams C, const double *q0, double tol, int nonlinear,
+                                                      int8_t *flags, int8_t *flag_acc)
+{
+    const long long n = (long long)C.nx * C.ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / C.nx), i = (int)(idx - (long long)j * C.nx);
+        size_t k = (size_t)j * C.pitch + i;
+        double B = C.B[k], h = q0[k];
+        bool wet;
+        double eta;
+        if (nonlinear) {
+            wet = h > C.dry_tol;
+            eta = (h + B) - C.sea_level;
+        } else {
+            wet = dmax(0.0, C.sea_level - B) > C.dry_tol;
+            eta = h;
+        }
+        const int8_t fl = (wet && fabs(eta) > tol) ? 1 : 0;
+        if (flags) flags[k] = fl;
+        if (flag_acc) flag_acc[k] = (int8_t)(flag_acc[k] | fl);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_max_speed(CellParams C, const double *q0, const double *q1,
                                                    const double *q2, int mode, unsigned long long *out)
 {
@@ -768,6 +793,14 @@ hipError_t launch_flag(const FlagParams &F, hipStream_t s)
 hipError_t launch_target(const CellParams &C, double xc, double yc, double R, int shape, hipStream_t s)
 {
     hipLaunchKernelGGL(k_target, dim3(grid_cells((long long)C.nx * C.ny)), dim3(256), 0, s, C, xc, yc, R, shape);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_flag(const CellParams &C, const double *q0, double tol, int nonlinear, int8_t *flags,
+                               int8_t *flag_acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_surface_flag, dim3(grid_cells((long long)C.nx * C.ny)), dim3(256), 0, s, C, q0, tol,
+                       nonlinear, flags, flag_acc);
     return hipGetLastError();
 }
 

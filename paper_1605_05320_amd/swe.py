@@ -50,7 +50,8 @@ class swe_problem(C.Structure):
                 ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
                 ("flag_every", C.c_int32), ("reserved", C.c_int32),
                 ("frames", C.c_void_p), ("q_out", swe_fields), ("flags_at", C.c_void_p),
-                ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p)]
+                ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
+                ("surface_tol", C.c_double), ("surface_flags_at", C.c_void_p)]
 
 
 class swe_result(C.Structure):
@@ -106,7 +107,7 @@ def lib():
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
                      "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
-                     "swe_serve"):
+                     "swe_serve", "swe_surface_flag"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_serve_footprint.restype = C.c_size_t
@@ -211,8 +212,14 @@ def adj_flag(grid: Grid, prm: Params, B, q, frames, K, k_lo, k_hi, tol, flags=No
                           _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc), _stream(stream)))
 
 
+def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=None, stream=None):
+    _check(lib().swe_surface_flag(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), C.c_double(tol),
+                                  _ptr(flags), _ptr(flag_acc), _stream(stream)))
+
+
 def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, frames, q_out,
-                 flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS) -> swe_problem:
+                 flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS,
+                 surface_tol=0.0, surface_flags_at=None) -> swe_problem:
     pb = swe_problem()
     pb.grid = grid.c()
     pb.params = prm.c()
@@ -227,8 +234,10 @@ def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, f
     pb.flags_at = None if flags_at is None else flags_at.data_ptr()
     pb.flag_acc = None if flag_acc is None else flag_acc.data_ptr()
     pb.maxip_acc = None if maxip_acc is None else maxip_acc.data_ptr()
+    pb.surface_tol = surface_tol
+    pb.surface_flags_at = None if surface_flags_at is None else surface_flags_at.data_ptr()
     # the problem holds raw device pointers: keep the tensors alive with it
-    pb._keep = (B, eta0, frames, tuple(q_out), flags_at, flag_acc, maxip_acc)
+    pb._keep = (B, eta0, frames, tuple(q_out), flags_at, flag_acc, maxip_acc, surface_flags_at)
     return pb
 
 

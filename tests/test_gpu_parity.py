@@ -253,6 +253,30 @@ def test_flag_parity_bit_exact(oracle, S, twod):
     assert np.array_equal(host(acc_g), acc_c) and np.array_equal(host(macc_g), macc_c)
 
 
+@pytest.mark.parametrize("twod", [True, False])
+def test_surface_flag_parity(oracle, S, twod):
+    O = oracle
+    rng = np.random.default_rng(21)
+    nx, ny = (203, 67) if twod else (777, 1)
+    B = -rng.uniform(-20.0, 300.0, (ny, nx))
+    if twod:
+        q0 = np.maximum(0.0, rng.normal(0, 0.3, (ny, nx)) - B)
+        model, ps = O.NONLINEAR, S.Params()
+    else:
+        q0 = rng.normal(0, 0.3, (ny, nx))
+        model, ps = O.LINEAR, S.Params(model=S.LINEAR)
+    go, gs = pair_grids(O, S, nx, ny, 100.0, 100.0)
+    acc_c = np.zeros((ny, nx), np.int8)
+    fl_c = O.surface_flag(go, O.Params(), model, B, q0, 0.25, acc_c)
+    fl_g = torch.full((ny, nx), 9, dtype=torch.int8, device=DEV)
+    acc_g = torch.zeros(ny, nx, dtype=torch.int8, device=DEV)
+    q = [dev(q0), torch.zeros(ny, nx, dtype=torch.float64, device=DEV),
+         torch.zeros(ny, nx, dtype=torch.float64, device=DEV)]
+    S.swe_surface_flag(gs, ps, dev(B), q if twod else q[:2], 0.25, fl_g, acc_g)
+    assert np.array_equal(host(fl_g), fl_c) and np.array_equal(host(acc_g), acc_c)
+    assert fl_c.any() and not fl_c.all()
+
+
 def test_window_matches_oracle(oracle, S):
     rng = np.random.default_rng(0)
     for _ in range(2000):
@@ -266,21 +290,25 @@ def test_window_matches_oracle(oracle, S):
 
 
 # --------------------------------------------------------------------------
-def _run_pair(O, S, go, gs, model, B, eta0, target, t0, ts, tf, K, tol, flag_every=1):
+def _run_pair(O, S, go, gs, model, B, eta0, target, t0, ts, tf, K, tol, flag_every=1, surface_tol=0.05):
     ncomp = 3 if go.ny > 1 else 2
-    rc = O.run(go, O.Params(), model, B, eta0, target, t0, ts, tf, K, tol, flag_every=flag_every)
+    rc = O.run(go, O.Params(), model, B, eta0, target, t0, ts, tf, K, tol, flag_every=flag_every,
+               surface_tol=surface_tol)
     ps = S.Params(model=S.NONLINEAR if go.ny > 1 else S.LINEAR)
     ny, nx = go.ny, go.nx
     frames = torch.zeros(K + 1, ncomp, ny, nx, dtype=torch.float64, device=DEV)
     q_out = [torch.zeros(ny, nx, dtype=torch.float64, device=DEV) for _ in range(ncomp)]
     flags_at = torch.zeros(K + 1, ny, nx, dtype=torch.int8, device=DEV)
+    sflags = torch.full((K + 1, ny, nx), 7, dtype=torch.int8, device=DEV)
     acc = torch.zeros(ny, nx, dtype=torch.int8, device=DEV)
     macc = torch.zeros(ny, nx, dtype=torch.float64, device=DEV)
     Bd, ed = dev(B.reshape(ny, nx)), dev(eta0.reshape(ny, nx))
     pb = S.make_problem(gs, ps, Bd, ed, target, t0, ts, tf, K, tol, frames, q_out, flags_at, acc, macc,
-                        flag_every=flag_every)
+                        flag_every=flag_every, surface_tol=surface_tol, surface_flags_at=sflags)
     ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, dtype=torch.float64, device=DEV)
     res = S.swe_run(pb, ws)
+    # surface flags at t0 and the output times, bit for bit (every frame written)
+    assert np.array_equal(host(sflags).reshape(rc.surface_flags_at.shape), rc.surface_flags_at)
     return rc, res, host(frames), [host(x) for x in q_out], host(flags_at), host(acc), host(macc)
 
 

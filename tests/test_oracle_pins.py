@@ -644,3 +644,61 @@ def test_run_1d_consistent(oracle):
     J_0 = (r.frames[K, 0].ravel() * q0[0].ravel() + r.frames[K, 1].ravel() * q0[1].ravel()).sum()
     assert abs(J_end - J_0) <= 0.05 * abs(J_0)
     assert r.flag_acc.any()
+
+
+# --------------------------------------------------------------------------
+# surface flagging (the criterion the adjoint flagging is compared with)
+# --------------------------------------------------------------------------
+def _brute_surface(model, B, q0, tol, sea_level=0.0, dry_tol=1e-3):
+    ny, nx = B.shape
+    fl = np.zeros((ny, nx), np.int8)
+    for j in range(ny):
+        for i in range(nx):
+            if model == 0:
+                wet = q0[j, i] > dry_tol
+                eta = (q0[j, i] + B[j, i]) - sea_level
+            else:
+                wet = max(0.0, sea_level - B[j, i]) > dry_tol
+                eta = q0[j, i]
+            fl[j, i] = 1 if (wet and abs(eta) > tol) else 0
+    return fl
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_surface_flags_brute_force(oracle, model):
+    O = oracle
+    rng = np.random.default_rng(7 + model)
+    nx, ny = 9, 6
+    B = -rng.uniform(-5.0, 100.0, (ny, nx))
+    if model == 0:
+        q0 = np.maximum(0.0, rng.normal(0, 0.2, (ny, nx)) - B)
+        q0[2, 3] = 0.0005                         # dry although the surface is far below sea level
+    else:
+        q0 = rng.normal(0, 0.2, (ny, nx))
+    g = O.Grid(nx, ny, 1.0, 1.0)
+    p = O.Params()
+    tol = 0.1
+    acc = np.zeros((ny, nx), np.int8)
+    fl = O.surface_flag(g, p, model, B, q0, tol, acc)
+    bf = _brute_surface(model, B, q0, tol)
+    assert np.array_equal(fl, bf) and np.array_equal(acc, bf)
+    assert bf.any() and not bf.all()
+    # troughs count as well as crests
+    eta = (q0 + B) if model == 0 else q0
+    assert (bf & (eta < 0)).any()
+
+
+def test_surface_flags_lake_at_rest_and_run(oracle):
+    O = oracle
+    b = I.basin(48, seed=3)
+    g = _grid2d(O, b)
+    p = O.Params()
+    h, hu, hv = O.init_state(g, p, O.NONLINEAR, b.B, np.zeros_like(b.B))
+    assert not O.surface_flag(g, p, O.NONLINEAR, b.B, h, 1e-12).any()
+    K, tf = 4, 1800.0
+    r = O.run(g, p, O.NONLINEAR, b.B, b.eta0, (b.target[0], b.target[1], 60e3), 0.0, 0.0, tf, K, 1e-4,
+              flag_every=2, surface_tol=0.05)
+    q0 = O.init_state(g, p, O.NONLINEAR, b.B, b.eta0)
+    assert np.array_equal(r.surface_flags_at[0], _brute_surface(0, b.B, q0[0], 0.05))
+    assert np.array_equal(r.surface_flags_at[K], _brute_surface(0, b.B, r.q[0], 0.05))
+    assert r.surface_flags_at[0].any()
