@@ -27,7 +27,8 @@
  *     cells; cell (i, j) is at offset j*pitch + i and has centre
  *     (x_lo + (i+1/2) dx, y_lo + (j+1/2) dy).  Boundary ghost cells are
  *     synthesised by the kernels from the boundary conditions.
- *   - ny == 1 selects the one-dimensional scheme (linear model and adjoint).
+ *   - ny == 1 selects the one-dimensional scheme (linear model and adjoint);
+ *     the linear model and the adjoint also run in 2D.
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream) and
  *     the call returns without waiting, except where stated.  Buffers must
  *     stay valid until the work has completed.
@@ -103,8 +104,11 @@ typedef struct {
  * h > dry_tol; a wet/dry interface is a wall (the dry side mirrors the wet
  * side); dry cells are not updated; after the update momenta are zeroed where
  * h <= dry_tol and negative depths are clamped to zero (counted).
- * Linear model (1D, ny == 1): eq. (hyp_linear) with A(x) of eq. (SWE_Aq) in
- * wave form.
+ * Linear model: in 1D (ny == 1) eq. (hyp_linear) with A(x) of eq. (SWE_Aq) in
+ * wave form; in 2D the equations of Sec. 5 linearized about the sea at rest,
+ * q = (eta, mu, gamma), wave form with transverse terms (the discrete
+ * transpose of adj_step at first order without transverse terms, and with
+ * them over constant depth).  Wet iff hbar = max(0, sea_level - B) > dry_tol.
  * `in` and `out` must not alias.  B is the bottom elevation plane.
  * `scal` (device, may be NULL) receives the Courant number of the step.
  */
@@ -326,7 +330,7 @@ SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_leve
 
 /*
  * swe_surface_flag - the surface criterion the adjoint flagging is compared
- * with (Sec. 7: refine where the sea surface relative to sea level exceeds a
+ * with (Sec. 6: refine where the sea surface relative to sea level exceeds a
  * tolerance): flags[k] = 1 if cell k is wet and |eta| > tol, else 0, with
  * eta = (h + B) - sea_level and wet = h > dry_tol for the nonlinear model, and
  * eta = q.f0, wet = max(0, sea_level - B) > dry_tol for the linear model.
@@ -418,7 +422,7 @@ SWE_API swe_status swe_serve(const swe_request *req, int32_t n, const swe_serve_
 /* Full problem of the two-phase driver. */
 typedef struct {
     swe_grid grid;
-    swe_params params;      /* params.model: NONLINEAR needs ny >= 2, LINEAR ny == 1 */
+    swe_params params;      /* params.model: NONLINEAR needs ny >= 2; LINEAR 1D or 2D */
     const double *B;        /* device bottom elevation */
     const double *eta0;     /* device initial surface */
     double target_xc, target_yc, target_R;

@@ -788,6 +788,99 @@ int or_lin_step(const or_grid *G, const or_params *P, const double *B,
     return step1d(G, P, B, q0, q1, o0, o1, dt, cfl_out, 0);
 }
 
+/*
+ * Linear forward, 2D (the 2D equations of Sec. 5 linearized about the sea at
+ * rest): q = (eta, mu, gamma), A1 = [[0,1,0],[g hbar,0,0],[0,0,0]] and A2 the
+ * same with the roles of mu and gamma exchanged.  Each edge is solved in its
+ * normal frame (eta, normal, tangential) with the two acoustic waves of
+ * lin_solve; the jump in the tangential momentum is a wave of speed 0, which
+ * carries no fluctuation and no correction.
+ * Transverse split of a physical fluctuation a on the edge that receives it,
+ * with the variable-coefficient eigenvectors of the edge's two cells,
+ * (1, -cL) at -cL from the low cell and (1, cR) at +cR from the high cell:
+ *   a = b1 (1, -cL) + b2 (1, cR):  b1 = (cR a_e - a_n)/(cL + cR),
+ *                                  b2 = (cL a_e + a_n)/(cL + cR)
+ *   positive part = cR b2 (1, cR, 0),  negative part = -cL b1 (1, -cL, 0)
+ * (each part is speed times wave, the wave form of the normal solve).
+ */
+static void lin2_split(const edge_t *e, int ydir, const double *a_ph, int positive, double *out_ph)
+{
+    double a[3];
+    to_normal(ydir, a_ph, a);
+    double nf[3];
+    if (positive) {
+        double b2 = (e->cl * a[0] + a[1]) * e->rc;
+        double k = e->cr * b2;
+        nf[0] = k; nf[1] = k * e->cr; nf[2] = 0.0;
+    } else {
+        double b1 = (e->cr * a[0] - a[1]) * e->rc;
+        double k = (-e->cl) * b1;
+        nf[0] = k; nf[1] = k * (-e->cl); nf[2] = 0.0;
+    }
+    to_phys(ydir, nf, out_ph);
+}
+
+static void lin2_split_cb(const edge_t *e, int ydir, const double *a, int positive, double *out)
+{
+    lin2_split(e, ydir, a, positive, out);
+}
+
+int or_lin_step2d(const or_grid *G, const or_params *P, const double *B,
+                  const double *q0, const double *q1, const double *q2,
+                  double *o0, double *o1, double *o2, double dt, double *cfl_out)
+{
+    int nx = G->nx, ny = G->ny;
+    if (nx < 1 || ny < 2 || !(dt > 0.0)) return -1;
+    pad_t Q[4] = {pad_new(nx, ny, 1), pad_new(nx, ny, 1), pad_new(nx, ny, 1), pad_new(nx, ny, 1)};
+    pad_load(&Q[0], q0);
+    pad_load(&Q[1], q1);
+    pad_load(&Q[2], q2);
+    pad_load(&Q[3], B);
+    fill_ghosts(Q, 4, G->bc, 1, 2);
+    size_t npad = (size_t)Q[0].px * Q[0].py;
+    lincoef_t *cf = (lincoef_t *)calloc(npad, sizeof(lincoef_t));
+    lin_coefs(&Q[3], P, cf);
+#define CF(i, j) (&cf[(size_t)((j) + 2) * Q[0].px + ((i) + 2)])
+    edges2d_t E = edges_new(nx, ny);
+#pragma omp parallel for schedule(static)
+    for (int j = -1; j <= ny; j++)
+        for (int i = -1; i <= nx + 1; i++) {
+            edge_t *e = XE(&E, i, j);
+            lin_solve(*PA(&Q[0], i - 1, j), *PA(&Q[1], i - 1, j), CF(i - 1, j),
+                      *PA(&Q[0], i, j), *PA(&Q[1], i, j), CF(i, j), e);
+            double am[3], ap[3];
+            memcpy(am, e->amdq, sizeof am);
+            memcpy(ap, e->apdq, sizeof ap);
+            to_phys(0, am, e->amdq);
+            to_phys(0, ap, e->apdq);
+        }
+#pragma omp parallel for schedule(static)
+    for (int j = -1; j <= ny + 1; j++)
+        for (int i = -1; i <= nx; i++) {
+            edge_t *e = YE(&E, i, j);
+            lin_solve(*PA(&Q[0], i, j - 1), *PA(&Q[2], i, j - 1), CF(i, j - 1),
+                      *PA(&Q[0], i, j), *PA(&Q[2], i, j), CF(i, j), e);
+            double am[3], ap[3];
+            memcpy(am, e->amdq, sizeof am);
+            memcpy(ap, e->apdq, sizeof ap);
+            to_phys(1, am, e->amdq);
+            to_phys(1, ap, e->apdq);
+        }
+    double nux = dt / G->dx, nuy = dt / G->dy;
+    unsigned char *wet = (unsigned char *)calloc((size_t)nx * ny, 1);
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) wet[(size_t)j * nx + i] = CF(i, j)->wet;
+#undef CF
+    double *out[3] = {o0, o1, o2};
+    update2d(&E, Q, 3, wet, nux, nuy, P->order, P->transverse, 0, lin2_split_cb, out);
+    if (cfl_out) *cfl_out = cfl2d(&E, nux, nuy);
+    edges_free(&E);
+    free(wet);
+    free(cf);
+    for (int c = 0; c < 4; c++) pad_free(&Q[c]);
+    return 0;
+}
+
 static void adj_split_cb(const edge_t *e, int ydir, const double *a, int positive, double *out)
 {
     adj_split(e, ydir, a, positive, out);
@@ -1041,7 +1134,7 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
 
 /*
  * Surface flagging, the default refinement criterion the adjoint method is
- * compared with (Sec. 7): a cell is flagged when the sea surface relative to
+ * compared with (Sec. 6): a cell is flagged when the sea surface relative to
  * sea level exceeds the tolerance, read here as |eta| > tol (a trough counts
  * as a wave as much as a crest), in cells that are wet.  eta = (h + B) -
  * sea_level, wet = h > dry_tol (nonlinear); eta = first component, wet =
@@ -1096,7 +1189,6 @@ int or_run(const or_problem *pb, or_result *res)
     memset(res, 0, sizeof(*res));
     if (K < 1 || !(pb->tf > pb->t0) || pb->flag_every < 1) return -1;
     if (!twod && pb->model != OR_LINEAR) return -1;
-    if (twod && pb->model != OR_NONLINEAR) return -1;
 
     /* phase A */
     double dt_adj = 0.0;
@@ -1151,6 +1243,8 @@ int or_run(const or_problem *pb, or_result *res)
         int ncl = 0;
         if (pb->model == OR_NONLINEAR)
             or_swe_step(G, P, pb->B, a[0], a[1], a[2], b[0], b[1], b[2], dt, &cfl, &ncl);
+        else if (twod)
+            or_lin_step2d(G, P, pb->B, a[0], a[1], a[2], b[0], b[1], b[2], dt, &cfl);
         else
             or_lin_step(G, P, pb->B, a[0], a[1], b[0], b[1], dt, &cfl);
         if (cfl > P->cfl_max) {

@@ -32,7 +32,7 @@ typedef struct {
 typedef struct {
     or_grid grid;
     or_params params;
-    int model;            /* OR_NONLINEAR (2D) or OR_LINEAR (1D) */
+    int model;            /* OR_NONLINEAR (2D) or OR_LINEAR (1D or 2D) */
     const double *B, *eta0;
     double target_xc, target_yc, target_R;
     int target_shape;     /* 0 Gaussian, 1 disk */
@@ -59,6 +59,9 @@ int or_swe_step(const or_grid *G, const or_params *P, const double *B,
 int or_lin_step(const or_grid *G, const or_params *P, const double *B,
                 const double *q0, const double *q1, double *o0, double *o1,
                 double dt, double *cfl_out);
+int or_lin_step2d(const or_grid *G, const or_params *P, const double *B,
+                  const double *q0, const double *q1, const double *q2,
+                  double *o0, double *o1, double *o2, double dt, double *cfl_out);
 int or_adj_step(const or_grid *G, const or_params *P, const double *B,
                 const double *q0, const double *q1, const double *q2,
                 double *o0, double *o1, double *o2, double dt, double *cfl_out);

@@ -157,6 +157,19 @@ def lin_step(grid: Grid, prm: Params, B, eta, mu, dt):
     return o[0], o[1], cfl.value
 
 
+def lin_step2d(grid: Grid, prm: Params, B, eta, mu, gamma, dt):
+    """One 2D linearized forward step.  Returns (eta, mu, gamma, cfl)."""
+    shp = (grid.ny, grid.nx)
+    B, eta, mu, gamma = (_f64(x, shp) for x in (B, eta, mu, gamma))
+    o = [np.empty(shp) for _ in range(3)]
+    cfl = C.c_double(0.0)
+    rc = lib().or_lin_step2d(C.byref(grid.c()), C.byref(prm.c()), _p(B), _p(eta), _p(mu), _p(gamma),
+                             _p(o[0]), _p(o[1]), _p(o[2]), C.c_double(dt), C.byref(cfl))
+    if rc != 0:
+        raise ValueError("or_lin_step2d failed")
+    return o[0], o[1], o[2], cfl.value
+
+
 def adj_step(grid: Grid, prm: Params, B, q0, q1, q2, dt):
     """One time-reversed adjoint step (1D if ny == 1).  Returns (q0, q1, q2, cfl)."""
     shp = (grid.ny, grid.nx)
@@ -251,7 +264,7 @@ class RunResult:
 
 
 def surface_flag(grid: Grid, prm: Params, model, B, q0, tol, flag_acc=None):
-    """Surface flags |eta| > tol in wet cells (the criterion of Sec. 7)."""
+    """Surface flags |eta| > tol in wet cells (the criterion of Sec. 6)."""
     shp = (grid.ny, grid.nx)
     B, q0 = _f64(B, shp), _f64(q0, shp)
     fl = np.zeros(shp, np.int8)

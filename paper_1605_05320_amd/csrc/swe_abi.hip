@@ -188,8 +188,6 @@ swe_status step_common(int model, const swe_grid *grid, const swe_params *prm, c
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SWE_E_INVAL, "dt must be finite and > 0");
     if (model == swe::MODEL_NL && grid->ny < 2)
         return fail(SWE_E_INVAL, "the nonlinear model is two-dimensional (ny >= 2)");
-    if (model == swe::MODEL_LIN && grid->ny != 1)
-        return fail(SWE_E_INVAL, "the linear forward model is one-dimensional (ny == 1)");
     swe::KParams k = make_kparams(grid, prm, B, in, out, dt, scal);
     HIP_TRY(swe::launch_step(model, k, (hipStream_t)stream));
     return SWE_OK;
@@ -297,7 +295,6 @@ static swe_status advance_impl(const swe_grid *grid, const swe_params *prm, cons
         return fail(SWE_E_INVAL, "need 0 < cfl_desired <= cfl_max");
     int model = prm->model == SWE_NONLINEAR ? swe::MODEL_NL : swe::MODEL_LIN;
     if (model == swe::MODEL_NL && grid->ny < 2) return fail(SWE_E_INVAL, "the nonlinear model needs ny >= 2");
-    if (model == swe::MODEL_LIN && grid->ny != 1) return fail(SWE_E_INVAL, "the linear model needs ny == 1");
     swe::FlagParams fp;
     swe::FlagCtl fc;
     if (fl) {
@@ -445,7 +442,6 @@ static swe_status check_problem(const swe_problem *pb)
     if (pb->flag_every < 1) return fail(SWE_E_INVAL, "flag_every must be >= 1");
     if (!(pb->target_R > 0.0)) return fail(SWE_E_INVAL, "target radius must be > 0");
     bool twod = pb->grid.ny > 1;
-    if (twod && pb->params.model != SWE_NONLINEAR) return fail(SWE_E_INVAL, "2D runs use the nonlinear model");
     if (!twod && pb->params.model != SWE_LINEAR) return fail(SWE_E_INVAL, "1D runs use the linear model");
     return SWE_OK;
 }

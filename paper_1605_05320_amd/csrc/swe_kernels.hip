@@ -714,6 +714,7 @@ hipError_t launch_step(int model, const KParams &P, hipStream_t s)
         dim3 grid(Q.nstrips * Q.nchunks);
         if (model == MODEL_NL) hipLaunchKernelGGL(k_march2d<NL>, grid, block, 0, s, Q);
         else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, Q);
+        else if (model == MODEL_LIN) hipLaunchKernelGGL(k_march2d<LIN2>, grid, block, 0, s, Q);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();

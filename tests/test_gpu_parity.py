@@ -173,6 +173,39 @@ def test_adj_step_parity_2d(oracle, S, n, ny, seed):
         assert close(x, y)
 
 
+@pytest.mark.parametrize("n,ny,seed,order,trans,bc", [
+    (150, 110, 3, 2, 1, (0, 0, 0, 0)),      # several strips and chunks, ragged tails
+    (64, 61, 7, 2, 0, (0, 1, 1, 0)),        # no transverse terms, outflow sides
+    (97, 40, 11, 1, 1, (0, 0, 0, 0)),
+])
+def test_lin2d_step_parity(oracle, S, n, ny, seed, order, trans, bc):
+    """2D linear forward (wave form) against the oracle, 8 steps."""
+    O = oracle
+    b = I.basin(n, seed, ny=ny)
+    go, gs = pair_grids(O, S, n, ny, b.grid.dx, b.grid.dy, bc)
+    po = O.Params(order=order, transverse=trans)
+    ps = S.Params(model=S.LINEAR, order=order, transverse=trans)
+    rng = np.random.default_rng(seed)
+    q = list(O.init_state(go, po, O.LINEAR, b.B, b.eta0))
+    q[1] = 50.0 * rng.standard_normal(q[1].shape) * (q[0] != 0)
+    q[2] = 50.0 * rng.standard_normal(q[2].shape) * (q[0] != 0)
+    dt = 0.5 * O.dt0(go, po, O.LINEAR, b.B, *q)
+    qc = list(q)
+    for _ in range(8):
+        qc = list(O.lin_step2d(go, po, b.B, qc[0], qc[1], qc[2], dt)[:3])
+    Bd = dev(b.B)
+    a = [dev(x) for x in q]
+    bb = [torch.empty_like(x) for x in a]
+    for _ in range(8):
+        S.swe_step(gs, ps, Bd, a, bb, dt)
+        a, bb = bb, a
+    qg = [host(x) for x in a]
+    exact = all(np.array_equal(x, y) for x, y in zip(qg, qc))
+    print(f"lin 2d {n}x{ny}: bit-exact={exact}")
+    for x, y in zip(qg, qc):
+        assert close(x, y)
+
+
 @pytest.mark.parametrize("n,order", [(2000, 2), (333, 2), (61, 1)])
 def test_1d_parity(oracle, S, n, order):
     O = oracle
@@ -294,7 +327,7 @@ def _run_pair(O, S, go, gs, model, B, eta0, target, t0, ts, tf, K, tol, flag_eve
     ncomp = 3 if go.ny > 1 else 2
     rc = O.run(go, O.Params(), model, B, eta0, target, t0, ts, tf, K, tol, flag_every=flag_every,
                surface_tol=surface_tol)
-    ps = S.Params(model=S.NONLINEAR if go.ny > 1 else S.LINEAR)
+    ps = S.Params(model=S.LINEAR if model == O.LINEAR else S.NONLINEAR)
     ny, nx = go.ny, go.nx
     frames = torch.zeros(K + 1, ncomp, ny, nx, dtype=torch.float64, device=DEV)
     q_out = [torch.zeros(ny, nx, dtype=torch.float64, device=DEV) for _ in range(ncomp)]
@@ -332,6 +365,25 @@ def test_run_1d_parity(oracle, S):
     assert close(q[0].ravel(), rc.q[0].ravel()) and close(q[1].ravel(), rc.q[1].ravel())
     assert close(macc.ravel(), rc.maxip_acc.ravel())
     assert _flags_match(acc.ravel(), rc.flag_acc.ravel(), rc.maxip_acc.ravel(), 1e-3)
+    assert rc.flag_acc.any()
+
+
+def test_run_2d_linear_parity(oracle, S):
+    """The two-phase driver with the 2D linear forward."""
+    O = oracle
+    n = 80
+    b = I.basin(n, 5)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    rc, res, frames, q, flags_at, acc, macc = _run_pair(O, S, go, gs, O.LINEAR, b.B, b.eta0,
+                                                         (b.target[0], b.target[1], 60e3),
+                                                         0.0, 1800.0, 5400.0, 12, 1e-4, flag_every=2)
+    assert res.n_sub == rc.n_sub and res.n_fwd_steps == rc.n_fwd_steps and res.t_end == rc.t_end
+    assert res.n_flag_calls == rc.n_flag_calls
+    assert close(frames, rc.frames)
+    for x, y in zip(q, rc.q):
+        assert close(x, y)
+    assert close(macc, rc.maxip_acc)
+    assert _flags_match(acc, rc.flag_acc, rc.maxip_acc, 1e-4)
     assert rc.flag_acc.any()
 
 
