@@ -341,6 +341,27 @@ SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_leve
 SWE_API swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
                                     double tol, int8_t *flags, int8_t *flag_acc, void *stream);
 
+/*
+ * adj_flag_interp - adj_flag with the snapshots on the adjoint's own grid
+ * (Sec. 4: the adjoint is solved at a fixed, usually coarser resolution and
+ * its values at the forward grid's locations come from linear, in 2D
+ * bilinear, interpolation on the snapshot grid; Sec. 6: a cell that is wet in
+ * the forward and dry in the adjoint problem gets inner product 0).
+ * For forward cell (i, j) with centre x = x_lo + (i + 1/2) dx (y likewise),
+ * on each axis of the adjoint grid u = (x - adj.x_lo)/adj.dx: the adjoint
+ * cell is clamp(floor(u), 0, n-1) and the interpolation uses centres i0 and
+ * i0 + 1 with i0 = clamp(floor(u - 1/2), 0, n-2) and weight
+ * w = clamp(u - 1/2 - i0, 0, 1) (constant beyond the outermost centres);
+ * q^ = (1-wy)((1-wx) q00 + wx q10) + wy((1-wx) q01 + wx q11).  The cell is
+ * adjoint-wet iff max(0, sea_level - adj_B) > dry_tol in its adjoint cell.
+ * frames: (K+1) * ncomp planes with adj_grid's pitch.  Other arguments and
+ * errors as adj_flag.  Enqueue only.
+ */
+SWE_API swe_status adj_flag_interp(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                                   const swe_grid *adj_grid, const double *adj_B, const double *frames,
+                                   int32_t K, int32_t k_lo, int32_t k_hi, double tol, int8_t *flags,
+                                   double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream);
+
 /* Flagging of a device-controlled forward run (see swe_advance_flagged). */
 typedef struct {
     const double *frames;   /* (K+1) snapshots, as for adj_flag */
@@ -350,6 +371,8 @@ typedef struct {
     int8_t *flags_final;    /* flags of the attempt that reaches t_out (nullable) */
     int8_t *flag_acc;       /* OR of all flags (nullable) */
     double *maxip_acc;      /* max of all m (nullable) */
+    const swe_grid *adj_grid;  /* snapshots on a grid of their own (as adj_flag_interp); NULL: the forward grid */
+    const double *adj_B;       /* bottom on adj_grid (with adj_grid) */
 } swe_flagging;
 
 /*
@@ -432,7 +455,7 @@ typedef struct {
     double tol;             /* flagging tolerance */
     int32_t flag_every;     /* flag after every flag_every accepted steps (>= 1) */
     int32_t reserved;
-    double *frames;         /* device, (K+1)*ncomp*ny*pitch doubles (output) */
+    double *frames;         /* device, (K+1)*ncomp*ny*pitch doubles of the adjoint grid (output) */
     swe_fields q_out;       /* device, final forward state (output) */
     int8_t *flags_at;       /* device, (K+1)*ny*pitch: flags at t0 + j ds; nullable */
     int8_t *flag_acc;       /* device plane, OR of all flags (caller zeroes); nullable */
@@ -440,6 +463,10 @@ typedef struct {
     double surface_tol;     /* tolerance of the surface criterion (with surface_flags_at) */
     int8_t *surface_flags_at; /* device, (K+1)*ny*pitch: swe_surface_flag at t0 + j ds, for
                                  comparison with flags_at; nullable */
+    swe_grid adj_grid;      /* adj_grid.nx == 0: the adjoint runs on the forward grid; else on this
+                               grid (same dimension, its own resolution), frames have its size and
+                               the flags interpolate the snapshots (adj_flag_interp) */
+    const double *adj_B;    /* device bottom on adj_grid (with adj_grid) */
 } swe_problem;
 
 typedef struct {

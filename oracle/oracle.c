@@ -1133,6 +1133,105 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
 }
 
 /*
+ * Adjoint values at the forward grid's cell centres when the adjoint was
+ * solved on a grid of its own (Sec. 4: linear, in 2D bilinear, interpolation
+ * from the data on the snapshot grid).  On each axis, for a point x and an
+ * adjoint axis of n centres x_lo + (c + 1/2) d:
+ *   u = (x - x_lo)/d;  containing cell ic = clamp(floor(u), 0, n-1);
+ *   i0 = clamp(floor(u - 1/2), 0, n-2) (0 if n = 1);
+ *   w = clamp(u - 1/2 - i0, 0, 1) (0 if n = 1): constant beyond the outer centres.
+ */
+static void interp_axis(double x, double x_lo, double d, int n, int *i0, double *w, int *ic)
+{
+    double u = (x - x_lo) / d;
+    double c = floor(u);
+    if (c < 0.0) c = 0.0;
+    if (c > n - 1) c = n - 1;
+    *ic = (int)c;
+    double xi = u - 0.5;
+    double f = floor(xi);
+    double top = (n >= 2) ? (double)(n - 2) : 0.0;
+    if (f < 0.0) f = 0.0;
+    if (f > top) f = top;
+    *i0 = (int)f;
+    double ww = (n >= 2) ? xi - f : 0.0;
+    if (ww < 0.0) ww = 0.0;
+    if (ww > 1.0) ww = 1.0;
+    *w = ww;
+}
+
+/* value of the adjoint-grid plane v at the centre of forward cell (i, j):
+ * (1-wy)((1-wx) v00 + wx v10) + wy((1-wx) v01 + wx v11), 1D: (1-wx) v0 + wx v1 */
+static double interp_at(const or_grid *G, const or_grid *Ga, const double *v, int i, int j)
+{
+    int i0, ic, j0 = 0, jc = 0;
+    double wx, wy = 0.0;
+    double x = G->x_lo + (i + 0.5) * G->dx;
+    interp_axis(x, Ga->x_lo, Ga->dx, Ga->nx, &i0, &wx, &ic);
+    int i1 = (Ga->nx >= 2) ? i0 + 1 : i0;
+    if (G->ny > 1) {
+        double y = G->y_lo + (j + 0.5) * G->dy;
+        interp_axis(y, Ga->y_lo, Ga->dy, Ga->ny, &j0, &wy, &jc);
+        int j1 = (Ga->ny >= 2) ? j0 + 1 : j0;
+        double v00 = v[(size_t)j0 * Ga->nx + i0], v10 = v[(size_t)j0 * Ga->nx + i1];
+        double v01 = v[(size_t)j1 * Ga->nx + i0], v11 = v[(size_t)j1 * Ga->nx + i1];
+        return (1.0 - wy) * ((1.0 - wx) * v00 + wx * v10) + wy * ((1.0 - wx) * v01 + wx * v11);
+    }
+    return (1.0 - wx) * v[i0] + wx * v[i1];
+}
+
+void or_interp(const or_grid *G, const or_grid *Ga, const double *v, double *out)
+{
+    for (int j = 0; j < G->ny; j++)
+        for (int i = 0; i < G->nx; i++) out[(size_t)j * G->nx + i] = interp_at(G, Ga, v, i, j);
+}
+
+/*
+ * or_flag with the snapshots on the adjoint grid Ga (bottom Ba): the inner
+ * product uses the interpolated snapshot values; the cell is adjoint-wet iff
+ * the adjoint cell containing its centre is wet (Sec. 6: wet in the forward
+ * and dry in the adjoint problem gives 0).
+ */
+void or_flag_interp(const or_grid *G, const or_params *P, int model, const double *B,
+                    const double *q0, const double *q1, const double *q2,
+                    const or_grid *Ga, const double *Ba, const double *frames, int K, int k_lo, int k_hi,
+                    double tol, signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc)
+{
+    (void)K;
+    int twod = G->ny > 1;
+    int ncomp = twod ? 3 : 2;
+    size_t na = (size_t)Ga->nx * Ga->ny;
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < G->ny; j++) {
+        for (int i = 0; i < G->nx; i++) {
+            size_t k = (size_t)j * G->nx + i;
+            int fwd_wet = (model == OR_NONLINEAR) ? (q0[k] > P->dry_tol)
+                                                  : (MAXD(0.0, P->sea_level - B[k]) > P->dry_tol);
+            int i0, ic, jc = 0, j0 = 0;
+            double w;
+            interp_axis(G->x_lo + (i + 0.5) * G->dx, Ga->x_lo, Ga->dx, Ga->nx, &i0, &w, &ic);
+            if (twod) interp_axis(G->y_lo + (j + 0.5) * G->dy, Ga->y_lo, Ga->dy, Ga->ny, &j0, &w, &jc);
+            int adj_wet = MAXD(0.0, P->sea_level - Ba[(size_t)jc * Ga->nx + ic]) > P->dry_tol;
+            double m = 0.0;
+            if (adj_wet && fwd_wet) {
+                double eta = (model == OR_NONLINEAR) ? (q0[k] + B[k]) - P->sea_level : q0[k];
+                for (int f = k_lo; f <= k_hi; f++) {
+                    const double *fr = frames + (size_t)f * ncomp * na;
+                    double ip = eta * interp_at(G, Ga, fr, i, j) + q1[k] * interp_at(G, Ga, fr + na, i, j);
+                    if (twod) ip = ip + q2[k] * interp_at(G, Ga, fr + 2 * na, i, j);
+                    m = MAXD(m, fabs(ip));
+                }
+            }
+            signed char fl = (m > tol) ? 1 : 0;
+            if (flags) flags[k] = fl;
+            if (maxip) maxip[k] = m;
+            if (flag_acc) flag_acc[k] = (signed char)(flag_acc[k] | fl);
+            if (maxip_acc) maxip_acc[k] = MAXD(maxip_acc[k], m);
+        }
+    }
+}
+
+/*
  * Surface flagging, the default refinement criterion the adjoint method is
  * compared with (Sec. 6): a cell is flagged when the sea surface relative to
  * sea level exceeds the tolerance, read here as |eta| > tol (a trough counts
@@ -1190,26 +1289,36 @@ int or_run(const or_problem *pb, or_result *res)
     if (K < 1 || !(pb->tf > pb->t0) || pb->flag_every < 1) return -1;
     if (!twod && pb->model != OR_LINEAR) return -1;
 
-    /* phase A */
+    /* phase A, on the adjoint's own grid if one is given */
+    int interp = pb->adj_grid.nx != 0;
+    const or_grid *GA = interp ? &pb->adj_grid : G;
+    const double *BA = interp ? pb->adj_B : pb->B;
+    if (interp && ((GA->ny > 1) != twod || !BA)) return -1;
+    size_t na = (size_t)GA->nx * GA->ny;
+    size_t nmax = na > n ? na : n;
     double dt_adj = 0.0;
-    int nsub = or_adj_nsub(G, P, pb->B, pb->t0, pb->tf, K, &dt_adj);
+    int nsub = or_adj_nsub(GA, P, BA, pb->t0, pb->tf, K, &dt_adj);
     if (nsub < 1) return -1;
     double *a[3], *b[3];
     for (int c = 0; c < 3; c++) {
-        a[c] = (double *)calloc(n, sizeof(double));
-        b[c] = (double *)calloc(n, sizeof(double));
+        a[c] = (double *)calloc(nmax, sizeof(double));
+        b[c] = (double *)calloc(nmax, sizeof(double));
     }
-    or_target(G, P, pb->B, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape, a[0]);
-    for (int c = 0; c < ncomp; c++) memcpy(pb->frames + (size_t)c * n, a[c], n * sizeof(double));
+    or_target(GA, P, BA, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape, a[0]);
+    for (int c = 0; c < ncomp; c++) memcpy(pb->frames + (size_t)c * na, a[c], na * sizeof(double));
     for (int k = 1; k <= K; k++) {
         for (int s = 0; s < nsub; s++) {
             double cfl;
-            or_adj_step(G, P, pb->B, a[0], a[1], a[2], b[0], b[1], b[2], dt_adj, &cfl);
+            or_adj_step(GA, P, BA, a[0], a[1], a[2], b[0], b[1], b[2], dt_adj, &cfl);
             for (int c = 0; c < 3; c++) { double *t = a[c]; a[c] = b[c]; b[c] = t; }
             res->n_adj_steps++;
         }
         for (int c = 0; c < ncomp; c++)
-            memcpy(pb->frames + ((size_t)k * ncomp + c) * n, a[c], n * sizeof(double));
+            memcpy(pb->frames + ((size_t)k * ncomp + c) * na, a[c], na * sizeof(double));
+    }
+    for (int c = 0; c < 3; c++) {
+        memset(a[c], 0, nmax * sizeof(double));
+        memset(b[c], 0, nmax * sizeof(double));
     }
     res->n_sub = nsub;
     res->dt_adj = dt_adj;
@@ -1223,8 +1332,12 @@ int or_run(const or_problem *pb, or_result *res)
 #define DO_FLAG(store_idx) do { \
         int ok = or_window(t, pb->t0, pb->ts, pb->tf, K, &klo, &khi); \
         if (!ok) { klo = 1; khi = 0; } \
-        or_flag(G, P, pb->model, pb->B, a[0], a[1], a[2], pb->frames, K, klo, khi, pb->tol, \
-                fl, NULL, pb->flag_acc, pb->maxip_acc); \
+        if (interp) \
+            or_flag_interp(G, P, pb->model, pb->B, a[0], a[1], a[2], GA, BA, pb->frames, K, klo, khi, \
+                           pb->tol, fl, NULL, pb->flag_acc, pb->maxip_acc); \
+        else \
+            or_flag(G, P, pb->model, pb->B, a[0], a[1], a[2], pb->frames, K, klo, khi, pb->tol, \
+                    fl, NULL, pb->flag_acc, pb->maxip_acc); \
         if ((store_idx) >= 0 && pb->flags_at) memcpy(pb->flags_at + (size_t)(store_idx) * n, fl, n); \
         if ((store_idx) >= 0 && pb->surface_flags_at) \
             or_surface_flag(G, P, pb->model, pb->B, a[0], pb->surface_tol, \

@@ -38,13 +38,15 @@ typedef struct {
     int target_shape;     /* 0 Gaussian, 1 disk */
     double t0, ts, tf, tol;
     int K, flag_every;
-    double *frames;       /* (K+1) * ncomp * nx * ny */
+    double *frames;       /* (K+1) * ncomp planes of the adjoint grid */
     double *q_out[3];
     signed char *flags_at;  /* (K+1) * nx * ny, nullable */
     signed char *flag_acc;  /* nullable */
     double *maxip_acc;      /* nullable */
     double surface_tol;             /* tolerance of the surface criterion */
     signed char *surface_flags_at;  /* (K+1) * nx * ny surface flags at t0 and the output times, nullable */
+    or_grid adj_grid;               /* nx == 0: the adjoint runs on the forward grid; else on this one */
+    const double *adj_B;            /* bottom on adj_grid */
 } or_problem;
 
 typedef struct {
@@ -80,6 +82,11 @@ void or_flag(const or_grid *G, const or_params *P, int model, const double *B,
              signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc);
 void or_surface_flag(const or_grid *G, const or_params *P, int model, const double *B,
                      const double *q0, double tol, signed char *flags, signed char *flag_acc);
+void or_interp(const or_grid *G, const or_grid *Ga, const double *v, double *out);
+void or_flag_interp(const or_grid *G, const or_params *P, int model, const double *B,
+                    const double *q0, const double *q1, const double *q2,
+                    const or_grid *Ga, const double *Ba, const double *frames, int K, int k_lo, int k_hi,
+                    double tol, signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc);
 int or_run(const or_problem *pb, or_result *res);
 
 #ifdef __cplusplus

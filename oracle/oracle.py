@@ -58,7 +58,8 @@ class _Problem(C.Structure):
                 ("K", C.c_int), ("flag_every", C.c_int),
                 ("frames", _dp), ("q_out", _dp * 3),
                 ("flags_at", _bp), ("flag_acc", _bp), ("maxip_acc", _dp),
-                ("surface_tol", C.c_double), ("surface_flags_at", _bp)]
+                ("surface_tol", C.c_double), ("surface_flags_at", _bp),
+                ("adj_grid", _Grid), ("adj_B", _dp)]
 
 
 class _Result(C.Structure):
@@ -263,6 +264,31 @@ class RunResult:
     extra: dict = field(default_factory=dict)
 
 
+def interp(grid: Grid, adj_grid: Grid, v):
+    """Adjoint-grid plane v at the centres of grid (linear/bilinear, Sec. 4)."""
+    v = _f64(v, (adj_grid.ny, adj_grid.nx))
+    out = np.empty((grid.ny, grid.nx))
+    lib().or_interp(C.byref(grid.c()), C.byref(adj_grid.c()), _p(v), _p(out))
+    return out
+
+
+def flag_interp(grid: Grid, prm: Params, model, B, q0, q1, q2, adj_grid: Grid, adj_B, frames, K, k_lo, k_hi,
+                tol, flag_acc=None, maxip_acc=None):
+    """flag() with the snapshots on adj_grid.  Returns (flags, maxip)."""
+    shp = (grid.ny, grid.nx)
+    B, q0, q1 = (_f64(x, shp) for x in (B, q0, q1))
+    q2 = _f64(q2, shp) if q2 is not None else np.zeros(shp)
+    adj_B = _f64(adj_B, (adj_grid.ny, adj_grid.nx))
+    frames = np.ascontiguousarray(frames, dtype=np.float64)
+    fl = np.zeros(shp, np.int8)
+    mx = np.zeros(shp)
+    lib().or_flag_interp(C.byref(grid.c()), C.byref(prm.c()), C.c_int(model), _p(B), _p(q0), _p(q1), _p(q2),
+                         C.byref(adj_grid.c()), _p(adj_B), _p(frames), C.c_int(K), C.c_int(k_lo),
+                         C.c_int(k_hi), C.c_double(tol), _b(fl), _p(mx), _b(flag_acc),
+                         _p(maxip_acc) if maxip_acc is not None else None)
+    return fl, mx
+
+
 def surface_flag(grid: Grid, prm: Params, model, B, q0, tol, flag_acc=None):
     """Surface flags |eta| > tol in wet cells (the criterion of Sec. 6)."""
     shp = (grid.ny, grid.nx)
@@ -274,14 +300,15 @@ def surface_flag(grid: Grid, prm: Params, model, B, q0, tol, flag_acc=None):
 
 
 def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
-        flag_every=1, target_shape=GAUSS, surface_tol=None) -> RunResult:
+        flag_every=1, target_shape=GAUSS, surface_tol=None, adj_grid: Grid = None, adj_B=None) -> RunResult:
     """Adjoint snapshots then the forward run with flagging (Sec. 4); with
     surface_tol, also the surface flags at t0 and at the output times."""
     shp = (grid.ny, grid.nx)
     n = grid.nx * grid.ny
     ncomp = 3 if grid.ny > 1 else 2
     B, eta0 = _f64(B, shp), _f64(eta0, shp)
-    frames = np.zeros((K + 1, ncomp) + shp)
+    ashp = shp if adj_grid is None else (adj_grid.ny, adj_grid.nx)
+    frames = np.zeros((K + 1, ncomp) + ashp)
     q = [np.zeros(shp) for _ in range(3)]
     flags_at = np.zeros((K + 1,) + shp, np.int8)
     acc = np.zeros(shp, np.int8)
@@ -303,6 +330,9 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
     if surface_tol is not None:
         sflags = np.zeros((K + 1,) + shp, np.int8)
         pb.surface_tol, pb.surface_flags_at = surface_tol, _b(sflags)
+    if adj_grid is not None:
+        adj_B = _f64(adj_B, ashp)
+        pb.adj_grid, pb.adj_B = adj_grid.c(), _p(adj_B)
     res = _Result()
     lib().or_run(C.byref(pb), C.byref(res))
     del n

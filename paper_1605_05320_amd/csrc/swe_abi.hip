@@ -279,6 +279,8 @@ swe_status swe_ctl_retarget(swe_ctl *ctl, double t_out, void *stream)
     return SWE_OK;
 }
 
+static swe_status setup_interp(swe::FlagParams &f, const swe_grid *grid, const swe_grid *ag, const double *aB);
+
 static swe_status advance_impl(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields a,
                                swe_fields b, swe_ctl *ctl, int32_t n_attempts, const swe_flagging *fl,
                                void *stream)
@@ -309,6 +311,7 @@ static swe_status advance_impl(const swe_grid *grid, const swe_params *prm, cons
         fp.sea_level = prm->sea_level; fp.dry_tol = prm->dry_tol; fp.tol = fl->tol;
         fp.B = B; fp.frames = fl->frames;
         fp.flag_acc = fl->flag_acc; fp.maxip_acc = fl->maxip_acc;
+        if (fl->adj_grid && (st = setup_interp(fp, grid, fl->adj_grid, fl->adj_B)) != SWE_OK) return st;
         std::memset(&fc, 0, sizeof fc);
         fc.ctl = ctl; fc.K = fl->K; fc.flag_every = fl->flag_every;
         fc.cfl_desired = prm->cfl_desired; fc.cfl_max = prm->cfl_max;
@@ -371,9 +374,25 @@ swe_status adj_window(double t, double t0, double ts, double tf, int32_t K, int3
     return SWE_OK;
 }
 
-swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
-                    const double *frames, int32_t K, int32_t k_lo, int32_t k_hi, double tol,
-                    int8_t *flags, double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream)
+// Snapshots on a grid of their own: validate it and record its geometry.
+static swe_status setup_interp(swe::FlagParams &f, const swe_grid *grid, const swe_grid *ag, const double *aB)
+{
+    swe_status st;
+    if ((st = check_grid(ag)) != SWE_OK) return st;
+    if ((ag->ny > 1) != (grid->ny > 1)) return fail(SWE_E_INVAL, "adjoint grid of another dimension");
+    if (!aB) return fail(SWE_E_INVAL, "adjoint grid without its bottom");
+    f.interp = 1;
+    f.x_lo = grid->x_lo; f.y_lo = grid->y_lo; f.dx = grid->dx; f.dy = grid->dy;
+    f.anx = ag->nx; f.any = ag->ny; f.apitch = ag->pitch;
+    f.ax_lo = ag->x_lo; f.ay_lo = ag->y_lo; f.adx = ag->dx; f.ady = ag->dy;
+    f.aB = aB;
+    return SWE_OK;
+}
+
+static swe_status flag_common(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                              const swe_grid *ag, const double *aB, const double *frames, int32_t K, int32_t k_lo,
+                              int32_t k_hi, double tol, int8_t *flags, double *maxip, int8_t *flag_acc,
+                              double *maxip_acc, void *stream)
 {
     swe_status st;
     if ((st = check_grid(grid)) != SWE_OK) return st;
@@ -394,8 +413,27 @@ swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B
     f.sea_level = prm->sea_level; f.dry_tol = prm->dry_tol; f.tol = tol;
     f.B = B; f.q0 = q.f0; f.q1 = q.f1; f.q2 = q.f2; f.frames = frames;
     f.flags = flags; f.maxip = maxip; f.flag_acc = flag_acc; f.maxip_acc = maxip_acc;
+    if (ag && (st = setup_interp(f, grid, ag, aB)) != SWE_OK) return st;
     HIP_TRY(swe::launch_flag(f, (hipStream_t)stream));
     return SWE_OK;
+}
+
+swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                    const double *frames, int32_t K, int32_t k_lo, int32_t k_hi, double tol,
+                    int8_t *flags, double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream)
+{
+    return flag_common(grid, prm, B, q, nullptr, nullptr, frames, K, k_lo, k_hi, tol, flags, maxip, flag_acc,
+                       maxip_acc, stream);
+}
+
+swe_status adj_flag_interp(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
+                           const swe_grid *adj_grid, const double *adj_B, const double *frames, int32_t K,
+                           int32_t k_lo, int32_t k_hi, double tol, int8_t *flags, double *maxip, int8_t *flag_acc,
+                           double *maxip_acc, void *stream)
+{
+    if (!adj_grid) return fail(SWE_E_INVAL, "adj_grid is NULL");
+    return flag_common(grid, prm, B, q, adj_grid, adj_B, frames, K, k_lo, k_hi, tol, flags, maxip, flag_acc,
+                       maxip_acc, stream);
 }
 
 swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q, double tol,
@@ -441,6 +479,11 @@ static swe_status check_problem(const swe_problem *pb)
     if (!(pb->ts >= pb->t0 && pb->ts <= pb->tf)) return fail(SWE_E_INVAL, "need t0 <= ts <= tf");
     if (pb->flag_every < 1) return fail(SWE_E_INVAL, "flag_every must be >= 1");
     if (!(pb->target_R > 0.0)) return fail(SWE_E_INVAL, "target radius must be > 0");
+    if (pb->adj_grid.nx != 0) {
+        if ((st = check_grid(&pb->adj_grid)) != SWE_OK) return st;
+        if ((pb->adj_grid.ny > 1) != (pb->grid.ny > 1)) return fail(SWE_E_INVAL, "adjoint grid of another dimension");
+        if (!pb->adj_B) return fail(SWE_E_INVAL, "adjoint grid without its bottom adj_B");
+    }
     bool twod = pb->grid.ny > 1;
     if (!twod && pb->params.model != SWE_LINEAR) return fail(SWE_E_INVAL, "1D runs use the linear model");
     return SWE_OK;
@@ -448,7 +491,10 @@ static swe_status check_problem(const swe_problem *pb)
 
 static size_t ws_layout(const swe_problem *pb, Workspace *w, char *base)
 {
+    // the two state sets serve the adjoint sub-steps (on the adjoint grid) and the forward run
     size_t plane = (size_t)pb->grid.ny * pb->grid.pitch * sizeof(double);
+    if (pb->adj_grid.nx != 0)
+        plane = std::max(plane, (size_t)pb->adj_grid.ny * pb->adj_grid.pitch * sizeof(double));
     size_t off = 0;
     for (int c = 0; c < 3; ++c) {
         if (w) w->a[c] = (double *)(base + off);
@@ -504,11 +550,16 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     const int ncomp = twod ? 3 : 2;
     const size_t plane = (size_t)G->ny * G->pitch;
     const int K = pb->K;
+    // the adjoint's grid and bottom (the forward's unless a grid of its own is given)
+    const bool interp = pb->adj_grid.nx != 0;
+    const swe_grid *AG = interp ? &pb->adj_grid : G;
+    const double *AB = interp ? pb->adj_B : pb->B;
+    const size_t aplane = (size_t)AG->ny * AG->pitch;
     auto frame = [&](int k) {
         swe_fields f;
-        f.f0 = pb->frames + ((size_t)k * ncomp + 0) * plane;
-        f.f1 = pb->frames + ((size_t)k * ncomp + 1) * plane;
-        f.f2 = twod ? pb->frames + ((size_t)k * ncomp + 2) * plane : nullptr;
+        f.f0 = pb->frames + ((size_t)k * ncomp + 0) * aplane;
+        f.f1 = pb->frames + ((size_t)k * ncomp + 1) * aplane;
+        f.f2 = twod ? pb->frames + ((size_t)k * ncomp + 2) * aplane : nullptr;
         return f;
     };
     swe_fields A = {w.a[0], w.a[1], twod ? w.a[2] : nullptr};
@@ -516,7 +567,7 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
 
     // ---- phase A: adjoint snapshots
     HIP_TRY(hipMemsetAsync(w.speed, 0, sizeof(unsigned long long), s));
-    if ((st = swe_max_speed(G, P, pb->B, A, 1, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
+    if ((st = swe_max_speed(AG, P, AB, A, 1, (uint64_t *)w.speed, stream)) != SWE_OK) return st;
     unsigned long long spb = 0;
     HIP_TRY(hipMemcpyAsync(&spb, w.speed, sizeof spb, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -530,7 +581,7 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     double dt_adj = ds / nsub;
     res->n_sub = nsub;
     res->dt_adj = dt_adj;
-    if ((st = adj_target(G, P, pb->B, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape,
+    if ((st = adj_target(AG, P, AB, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape,
                          frame(0), stream)) != SWE_OK)
         return st;
     for (int k = 1; k <= K; ++k) {
@@ -538,7 +589,7 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         for (int sstep = 0; sstep < nsub; ++sstep) {
             bool last = sstep == nsub - 1;
             swe_fields dst = last ? frame(k) : ((sstep & 1) ? Bf : A);
-            if ((st = adj_step(G, P, pb->B, src, dst, dt_adj, nullptr, stream)) != SWE_OK) return st;
+            if ((st = adj_step(AG, P, AB, src, dst, dt_adj, nullptr, stream)) != SWE_OK) return st;
             res->n_adj_steps++;
             src = dst;
         }
@@ -552,8 +603,8 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         int32_t lo, hi;
         if ((st = adj_window(pb->t0, pb->t0, pb->ts, pb->tf, K, &lo, &hi)) != SWE_OK) return st;
         int8_t *fl0 = pb->flags_at ? pb->flags_at : w.flags;
-        if ((st = adj_flag(G, P, pb->B, cur, pb->frames, K, lo, hi, pb->tol, fl0, nullptr, pb->flag_acc,
-                           pb->maxip_acc, stream)) != SWE_OK)
+        if ((st = flag_common(G, P, pb->B, cur, interp ? AG : nullptr, AB, pb->frames, K, lo, hi, pb->tol, fl0,
+                              nullptr, pb->flag_acc, pb->maxip_acc, stream)) != SWE_OK)
             return st;
         if (pb->surface_flags_at &&
             (st = swe_surface_flag(G, P, pb->B, cur, pb->surface_tol, pb->surface_flags_at, nullptr, stream)) !=
@@ -574,6 +625,8 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     fl.t0 = pb->t0; fl.ts = pb->ts; fl.tf = pb->tf; fl.tol = pb->tol;
     fl.flag_acc = pb->flag_acc;
     fl.maxip_acc = pb->maxip_acc;
+    fl.adj_grid = interp ? AG : nullptr;
+    fl.adj_B = interp ? AB : nullptr;
     swe_ctl hc;
     for (int j = 1; j <= K; ++j) {
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;

@@ -22,6 +22,13 @@ struct FlagParams {
     double *maxip;
     int8_t *flag_acc;
     double *maxip_acc;
+    // snapshots on a grid of their own (interp != 0): the forward grid's
+    // geometry, the adjoint grid and its bottom; frames then have its pitch
+    int interp;
+    double x_lo, y_lo, dx, dy;
+    int anx, any, apitch;
+    double ax_lo, ay_lo, adx, ady;
+    const double *aB;
 };
 
 // Device-side flag scheduling after a controlled step attempt.

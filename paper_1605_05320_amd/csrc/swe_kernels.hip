@@ -482,24 +482,42 @@ __global__ void k_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_m
 // ---------------------------------------------------------------------------
 // Flagging pass: one thread per cell, coalesced across the row.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_flag(FlagParams F)
+// Interpolation position of coordinate x on an axis of n cell centres
+// x_lo + (c + 1/2) d: lower centre index i0 and weight w in [0, 1] (constant
+// beyond the outermost centres); and the index of the cell containing x.
+__device__ __forceinline__ void axis_weights(double x, double x_lo, double d, int n, int &i0, double &w, int &ic)
 {
-    const long long n = (long long)F.nx * F.ny;
-    const size_t plane = (size_t)F.ny * F.pitch;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-         idx += (long long)gridDim.x * blockDim.x) {
-        int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
-        size_t k = (size_t)j * F.pitch + i;
-        double B = F.B[k];
-        double hb = dmax(0.0, F.sea_level - B);
-        bool adj_wet = hb > F.dry_tol;
-        double q0 = F.q0[k];
-        bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
-        double m = 0.0;
+    const double u = (x - x_lo) / d;
+    double c = floor(u);
+    c = c < 0.0 ? 0.0 : (c > n - 1 ? (double)(n - 1) : c);
+    ic = (int)c;
+    const double xi = u - 0.5;
+    double f = floor(xi);
+    const double top = n >= 2 ? (double)(n - 2) : 0.0;
+    f = f < 0.0 ? 0.0 : (f > top ? top : f);
+    i0 = (int)f;
+    double ww = n >= 2 ? xi - f : 0.0;
+    w = ww < 0.0 ? 0.0 : (ww > 1.0 ? 1.0 : ww);
+}
+
+// m = max over the window's snapshots of |<q, q^_k>| at cell (i, j) (storage
+// index k), 0 where the forward or the adjoint cell is dry.  With snapshots on
+// their own grid, q^_k is interpolated (bilinear in 2D, linear in 1D) at the
+// cell centre and the adjoint cell is the one containing the centre.
+__device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size_t k)
+{
+    const double B = F.B[k];
+    const double q0 = F.q0[k];
+    double m = 0.0;
+    if (!F.interp) {
+        const size_t plane = (size_t)F.ny * F.pitch;
+        const double hb = dmax(0.0, F.sea_level - B);
+        const bool adj_wet = hb > F.dry_tol;
+        const bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
         if (adj_wet && fwd_wet) {
-            double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
-            double q1 = F.q1[k];
-            double q2 = F.twod ? F.q2[k] : 0.0;
+            const double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
+            const double q1 = F.q1[k];
+            const double q2 = F.twod ? F.q2[k] : 0.0;
             const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
             for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
                 double ip = eta * fr[0] + q1 * fr[plane];
@@ -507,6 +525,55 @@ __global__ void __launch_bounds__(256) k_flag(FlagParams F)
                 m = dmax(m, fabs(ip));
             }
         }
+        return m;
+    }
+    const bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : (dmax(0.0, F.sea_level - B) > F.dry_tol);
+    const double x = F.x_lo + (i + 0.5) * F.dx;
+    int i0, ic, j0 = 0, jc = 0;
+    double wx, wy = 0.0;
+    axis_weights(x, F.ax_lo, F.adx, F.anx, i0, wx, ic);
+    if (F.twod) {
+        const double y = F.y_lo + (j + 0.5) * F.dy;
+        axis_weights(y, F.ay_lo, F.ady, F.any, j0, wy, jc);
+    }
+    const bool adj_wet = dmax(0.0, F.sea_level - F.aB[(size_t)jc * F.apitch + ic]) > F.dry_tol;
+    if (!(adj_wet && fwd_wet)) return 0.0;
+    const double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
+    const double q1 = F.q1[k];
+    const double q2 = F.twod ? F.q2[k] : 0.0;
+    const size_t aplane = (size_t)F.any * F.apitch;
+    const int i1 = F.anx >= 2 ? i0 + 1 : i0;
+    const int j1 = F.twod && F.any >= 2 ? j0 + 1 : j0;
+    const size_t k00 = (size_t)j0 * F.apitch + i0, k10 = (size_t)j0 * F.apitch + i1;
+    const size_t k01 = (size_t)j1 * F.apitch + i0, k11 = (size_t)j1 * F.apitch + i1;
+    const double ux = 1.0 - wx, uy = 1.0 - wy;
+    const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * aplane;
+    for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * aplane) {
+        double v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c == 2 && !F.twod) { v[c] = 0.0; continue; }
+            const double *p = fr + (size_t)c * aplane;
+            if (F.twod)
+                v[c] = uy * (ux * p[k00] + wx * p[k10]) + wy * (ux * p[k01] + wx * p[k11]);
+            else
+                v[c] = ux * p[k00] + wx * p[k10];
+        }
+        double ip = eta * v[0] + q1 * v[1];
+        if (F.twod) ip = ip + q2 * v[2];
+        m = dmax(m, fabs(ip));
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(256) k_flag(FlagParams F)
+{
+    const long long n = (long long)F.nx * F.ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
+        size_t k = (size_t)j * F.pitch + i;
+        const double m = flag_m(F, i, j, k);
         int8_t fl = m > F.tol ? 1 : 0;
         if (F.flags) F.flags[k] = fl;
         if (F.maxip) F.maxip[k] = m;
@@ -561,28 +628,11 @@ __global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
     else       { F.q0 = C.a0; F.q1 = C.a1; F.q2 = C.a2; }
     F.flags = S.done ? C.flags_final : nullptr;
     const long long n = (long long)F.nx * F.ny;
-    const size_t plane = (size_t)F.ny * F.pitch;
     for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
          idx += (long long)gridDim.x * blockDim.x) {
         int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
         size_t k = (size_t)j * F.pitch + i;
-        double B = F.B[k];
-        double hb = dmax(0.0, F.sea_level - B);
-        bool adj_wet = hb > F.dry_tol;
-        double q0 = F.q0[k];
-        bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
-        double m = 0.0;
-        if (adj_wet && fwd_wet) {
-            double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
-            double q1 = F.q1[k];
-            double q2 = F.twod ? F.q2[k] : 0.0;
-            const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
-            for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
-                double ip = eta * fr[0] + q1 * fr[plane];
-                if (F.twod) ip = ip + q2 * fr[2 * plane];
-                m = dmax(m, fabs(ip));
-            }
-        }
+        const double m = flag_m(F, i, j, k);
         int8_t fl = m > F.tol ? 1 : 0;
         if (F.flags) F.flags[k] = fl;
         if (F.flag_acc) F.flag_acc[k] = (int8_t)(F.flag_acc[k] | fl);

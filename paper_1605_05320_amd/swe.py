@@ -51,7 +51,8 @@ class swe_problem(C.Structure):
                 ("flag_every", C.c_int32), ("reserved", C.c_int32),
                 ("frames", C.c_void_p), ("q_out", swe_fields), ("flags_at", C.c_void_p),
                 ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
-                ("surface_tol", C.c_double), ("surface_flags_at", C.c_void_p)]
+                ("surface_tol", C.c_double), ("surface_flags_at", C.c_void_p),
+                ("adj_grid", swe_grid), ("adj_B", C.c_void_p)]
 
 
 class swe_result(C.Structure):
@@ -107,7 +108,7 @@ def lib():
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
                      "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
-                     "swe_serve", "swe_surface_flag"):
+                     "swe_serve", "swe_surface_flag", "adj_flag_interp"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_serve_footprint.restype = C.c_size_t
@@ -212,6 +213,14 @@ def adj_flag(grid: Grid, prm: Params, B, q, frames, K, k_lo, k_hi, tol, flags=No
                           _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc), _stream(stream)))
 
 
+def adj_flag_interp(grid: Grid, prm: Params, B, q, adj_grid: Grid, adj_B, frames, K, k_lo, k_hi, tol, flags=None,
+                    maxip=None, flag_acc=None, maxip_acc=None, stream=None):
+    _check(lib().adj_flag_interp(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), C.byref(adj_grid.c()),
+                                 _ptr(adj_B), _ptr(frames), C.c_int32(K), C.c_int32(k_lo), C.c_int32(k_hi),
+                                 C.c_double(tol), _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc),
+                                 _stream(stream)))
+
+
 def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=None, stream=None):
     _check(lib().swe_surface_flag(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), C.c_double(tol),
                                   _ptr(flags), _ptr(flag_acc), _stream(stream)))
@@ -219,7 +228,7 @@ def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=No
 
 def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, frames, q_out,
                  flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS,
-                 surface_tol=0.0, surface_flags_at=None) -> swe_problem:
+                 surface_tol=0.0, surface_flags_at=None, adj_grid: Grid = None, adj_B=None) -> swe_problem:
     pb = swe_problem()
     pb.grid = grid.c()
     pb.params = prm.c()
@@ -236,8 +245,11 @@ def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, f
     pb.maxip_acc = None if maxip_acc is None else maxip_acc.data_ptr()
     pb.surface_tol = surface_tol
     pb.surface_flags_at = None if surface_flags_at is None else surface_flags_at.data_ptr()
+    if adj_grid is not None:
+        pb.adj_grid = adj_grid.c()
+        pb.adj_B = adj_B.data_ptr()
     # the problem holds raw device pointers: keep the tensors alive with it
-    pb._keep = (B, eta0, frames, tuple(q_out), flags_at, flag_acc, maxip_acc, surface_flags_at)
+    pb._keep = (B, eta0, frames, tuple(q_out), flags_at, flag_acc, maxip_acc, surface_flags_at, adj_B)
     return pb
 
 
@@ -281,15 +293,19 @@ def swe_advance(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, stream=N
 class swe_flagging(C.Structure):
     _fields_ = [("frames", C.c_void_p), ("K", C.c_int32), ("flag_every", C.c_int32),
                 ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
-                ("flags_final", C.c_void_p), ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p)]
+                ("flags_final", C.c_void_p), ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
+                ("adj_grid", C.POINTER(swe_grid)), ("adj_B", C.c_void_p)]
 
 
 def swe_advance_flagged(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, frames, K, flag_every,
-                        t0, ts, tf, tol, flags_final=None, flag_acc=None, maxip_acc=None, stream=None):
+                        t0, ts, tf, tol, flags_final=None, flag_acc=None, maxip_acc=None, adj_grid: Grid = None,
+                        adj_B=None, stream=None):
+    ag = None if adj_grid is None else C.pointer(adj_grid.c())
     fl = swe_flagging(frames.data_ptr(), K, flag_every, t0, ts, tf, tol,
                       None if flags_final is None else flags_final.data_ptr(),
                       None if flag_acc is None else flag_acc.data_ptr(),
-                      None if maxip_acc is None else maxip_acc.data_ptr())
+                      None if maxip_acc is None else maxip_acc.data_ptr(),
+                      ag, None if adj_B is None else adj_B.data_ptr())
     _check(lib().swe_advance_flagged(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                                      _ptr(ctl), C.c_int32(n_attempts), C.byref(fl), _stream(stream)))
 

@@ -310,6 +310,49 @@ def test_surface_flag_parity(oracle, S, twod):
     assert fl_c.any() and not fl_c.all()
 
 
+@pytest.mark.parametrize("twod", [True, False])
+def test_flag_interp_parity(oracle, S, twod):
+    """Snapshots on their own, coarser grid: bilinear (linear) interpolation
+    in the flag pass, bit for bit against the oracle."""
+    O = oracle
+    rng = np.random.default_rng(31)
+    if twod:
+        nx, ny, ncx, ncy = 157, 83, 61, 35
+        go = O.Grid(nx, ny, 800.0, 900.0, 0.0, -250.0)
+        gco = O.Grid(ncx, ncy, 2100.0, 2200.0, 150.0, -100.0)
+    else:
+        nx, ny, ncx, ncy = 901, 1, 301, 1
+        go = O.Grid(nx, 1, 200.0, 1.0, -400e3)
+        gco = O.Grid(ncx, 1, 600.0, 1.0, -400e3 + 37.0)
+    gs = S.Grid(go.nx, go.ny, go.dx, go.dy, go.x_lo, go.y_lo)
+    gcs = S.Grid(gco.nx, gco.ny, gco.dx, gco.dy, gco.x_lo, gco.y_lo)
+    K = 6
+    B = -rng.uniform(-20.0, 300.0, (ny, nx))
+    Bc = -rng.uniform(-20.0, 300.0, (ncy, ncx))
+    if twod:
+        q0 = np.maximum(0.0, rng.normal(0, 0.3, (ny, nx)) - B)
+        model, ps = O.NONLINEAR, S.Params()
+    else:
+        q0 = rng.normal(0, 0.3, (ny, nx))
+        model, ps = O.LINEAR, S.Params(model=S.LINEAR)
+    q1, q2 = rng.normal(0, 1, (ny, nx)), rng.normal(0, 1, (ny, nx))
+    ncomp = 3 if twod else 2
+    frames = rng.normal(0, 1e-3, (K + 1, ncomp, ncy, ncx))
+    tol = 2e-3
+    qd = [dev(q0), dev(q1), dev(q2)] if twod else [dev(q0), dev(q1)]
+    Bd, Bcd, fd = dev(B), dev(Bc), dev(frames)
+    for (lo, hi) in [(0, K), (2, 4), (1, 0)]:
+        fl_c, m_c = O.flag_interp(go, O.Params(), model, B, q0, q1, q2 if twod else None, gco, Bc, frames, K,
+                                  lo, hi, tol)
+        fl_g = torch.empty(ny, nx, dtype=torch.int8, device=DEV)
+        m_g = torch.empty(ny, nx, dtype=torch.float64, device=DEV)
+        S.adj_flag_interp(gs, ps, Bd, qd, gcs, Bcd, fd, K, lo, hi, tol, fl_g, m_g)
+        assert np.array_equal(host(fl_g), fl_c)
+        assert np.array_equal(host(m_g), m_c)
+        if lo <= hi:
+            assert fl_c.any()
+
+
 def test_window_matches_oracle(oracle, S):
     rng = np.random.default_rng(0)
     for _ in range(2000):
@@ -384,6 +427,38 @@ def test_run_2d_linear_parity(oracle, S):
         assert close(x, y)
     assert close(macc, rc.maxip_acc)
     assert _flags_match(acc, rc.flag_acc, rc.maxip_acc, 1e-4)
+    assert rc.flag_acc.any()
+
+
+def test_run_2d_coarse_adjoint_parity(oracle, S):
+    """The two-phase driver with the adjoint on a grid of half the
+    resolution (snapshots interpolated in every flag pass)."""
+    O = oracle
+    n, K, tol = 96, 10, 1e-4
+    b, bc = I.basin(n, 3), I.basin(n // 2, 3)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    gco, gcs = pair_grids(O, S, n // 2, n // 2, bc.grid.dx, bc.grid.dy)
+    tgt = (b.target[0], b.target[1], 60e3)
+    rc = O.run(go, O.Params(), O.NONLINEAR, b.B, b.eta0, tgt, 0.0, 1800.0, 5400.0, K, tol, flag_every=2,
+               adj_grid=gco, adj_B=bc.B)
+    frames = torch.zeros(K + 1, 3, n // 2, n // 2, dtype=torch.float64, device=DEV)
+    q_out = [torch.zeros(n, n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    flags_at = torch.zeros(K + 1, n, n, dtype=torch.int8, device=DEV)
+    acc = torch.zeros(n, n, dtype=torch.int8, device=DEV)
+    macc = torch.zeros(n, n, dtype=torch.float64, device=DEV)
+    pb = S.make_problem(gs, S.Params(), dev(b.B), dev(b.eta0), tgt, 0.0, 1800.0, 5400.0, K, tol, frames, q_out,
+                        flags_at, acc, macc, flag_every=2, adj_grid=gcs, adj_B=dev(bc.B))
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, dtype=torch.float64, device=DEV)
+    res = S.swe_run(pb, ws)
+    assert res.n_sub == rc.n_sub and res.n_adj_steps == rc.n_adj_steps
+    assert res.n_fwd_steps == rc.n_fwd_steps and res.n_flag_calls == rc.n_flag_calls
+    assert close(host(frames), rc.frames)
+    ok, exact = compare_nl(b.B, [host(x) for x in q_out], rc.q)
+    assert ok
+    assert close(host(macc), rc.maxip_acc)
+    assert _flags_match(host(acc), rc.flag_acc, rc.maxip_acc, tol)
+    for j in range(K + 1):
+        assert _flags_match(host(flags_at)[j], rc.flags_at[j], rc.maxip_acc, tol)
     assert rc.flag_acc.any()
 
 

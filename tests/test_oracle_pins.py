@@ -822,3 +822,149 @@ def test_invariance_2d_linear(oracle):
     d1 = _invariance_drift_2d_linear(oracle, 48, 2, 1)
     d2 = _invariance_drift_2d_linear(oracle, 96, 2, 1)
     assert d2 <= 0.025 and d1 / d2 >= 1.5
+
+
+# --------------------------------------------------------------------------
+# adjoint snapshots on a coarser grid: interpolation to the forward grid
+# --------------------------------------------------------------------------
+def _coarse_fine(O, r=2, twod=True):
+    nxc, nyc = 7, (5 if twod else 1)
+    dxc, dyc = 3072.0, (2048.0 if twod else 1.0)
+    x_lo, y_lo = -1000.0, 500.0
+    gc = O.Grid(nxc, nyc, dxc, dyc, x_lo, y_lo if twod else 0.0)
+    gf = O.Grid(nxc * r, nyc * r if twod else 1, dxc / r, dyc / r if twod else 1.0, x_lo, y_lo if twod else 0.0)
+    return gc, gf
+
+
+@pytest.mark.parametrize("twod", [True, False])
+def test_interp_reproduces_bilinear_fields(oracle, twod):
+    """Bilinear (linear in 1D) interpolation reproduces a bilinear field at
+    every point inside the hull of the adjoint cell centres, and extends the
+    boundary values as constants outside it."""
+    O = oracle
+    for r in (2, 3, 5):
+        gc, gf = _coarse_fine(O, r, twod)
+        xc = gc.x_lo + (np.arange(gc.nx) + 0.5) * gc.dx
+        yc = gc.y_lo + (np.arange(gc.ny) + 0.5) * gc.dy if twod else np.zeros(1)
+        f = lambda x, y: 0.3 + 2e-4 * x - 5e-5 * y + 1e-9 * x * y
+        XC, YC = np.meshgrid(xc, yc)
+        v = f(XC, YC)
+        out = O.interp(gf, gc, v)
+        xf = gf.x_lo + (np.arange(gf.nx) + 0.5) * gf.dx
+        yf = gf.y_lo + (np.arange(gf.ny) + 0.5) * gf.dy if twod else np.zeros(1)
+        Xe = np.clip(xf, xc[0], xc[-1])
+        Ye = np.clip(yf, yc[0], yc[-1])
+        XE, YE = np.meshgrid(Xe, Ye)
+        assert np.abs(out - f(XE, YE)).max() <= 1e-13 * np.abs(v).max()
+
+
+def test_interp_same_grid_is_identity(oracle):
+    O = oracle
+    g = O.Grid(9, 6, 1024.0, 512.0, 0.0, 0.0)
+    v = np.random.default_rng(3).normal(size=(6, 9))
+    assert np.array_equal(O.interp(g, g, v), v)
+
+
+def _brute_flags_interp(gf, gc, Bf, Bc, q, frames, lo, hi, tol, model=0, dry_tol=1e-3):
+    """Plain loops over the definition of adj_flag_interp."""
+    twod = gf.ny > 1
+
+    def axis(x, x_lo, d, n):
+        u = (x - x_lo) / d
+        ic = int(min(max(math.floor(u), 0), n - 1))
+        xi = u - 0.5
+        i0 = int(min(max(math.floor(xi), 0), max(n - 2, 0)))
+        w = min(max(xi - i0, 0.0), 1.0) if n >= 2 else 0.0
+        return ic, i0, (i0 + 1 if n >= 2 else i0), w
+
+    fl = np.zeros((gf.ny, gf.nx), np.int8)
+    mm = np.zeros((gf.ny, gf.nx))
+    for j in range(gf.ny):
+        for i in range(gf.nx):
+            ic, i0, i1, wx = axis(gf.x_lo + (i + 0.5) * gf.dx, gc.x_lo, gc.dx, gc.nx)
+            jc, j0, j1, wy = (axis(gf.y_lo + (j + 0.5) * gf.dy, gc.y_lo, gc.dy, gc.ny) if twod else (0, 0, 0, 0.0))
+            fwd = q[0][j, i] > dry_tol if model == 0 else max(0.0, -Bf[j, i]) > dry_tol
+            adj = max(0.0, -Bc[jc, ic]) > dry_tol
+            m = 0.0
+            if fwd and adj:
+                eta = (q[0][j, i] + Bf[j, i]) if model == 0 else q[0][j, i]
+                for k in range(lo, hi + 1):
+                    v = []
+                    for c in range(3 if twod else 2):
+                        p = frames[k, c]
+                        if twod:
+                            v.append((1.0 - wy) * ((1.0 - wx) * p[j0, i0] + wx * p[j0, i1])
+                                     + wy * ((1.0 - wx) * p[j1, i0] + wx * p[j1, i1]))
+                        else:
+                            v.append((1.0 - wx) * p[0, i0] + wx * p[0, i1])
+                    ip = eta * v[0] + q[1][j, i] * v[1]
+                    if twod:
+                        ip = ip + q[2][j, i] * v[2]
+                    m = max(m, abs(ip))
+            fl[j, i] = 1 if m > tol else 0
+            mm[j, i] = m
+    return fl, mm
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_flags_interp_brute_force(oracle, seed):
+    O = oracle
+    rng = np.random.default_rng(seed)
+    gc = O.Grid(6, 5, 3000.0, 2000.0, 100.0, -300.0)
+    gf = O.Grid(14, 11, 1250.0, 900.0, 0.0, -500.0)      # ratio not an integer, offset origin
+    K = 4
+    Bc = -rng.uniform(-5.0, 100.0, (gc.ny, gc.nx))
+    Bf = -rng.uniform(-5.0, 100.0, (gf.ny, gf.nx))
+    h = np.maximum(0.0, rng.normal(0, 0.2, (gf.ny, gf.nx)) - Bf)
+    q = [h, rng.normal(0, 1, h.shape), rng.normal(0, 1, h.shape)]
+    frames = rng.normal(0, 0.01, (K + 1, 3, gc.ny, gc.nx))
+    p = O.Params()
+    for (lo, hi) in [(0, K), (1, 2), (1, 0)]:
+        tol = 0.01
+        fl, m = O.flag_interp(gf, p, O.NONLINEAR, Bf, q[0], q[1], q[2], gc, Bc, frames, K, lo, hi, tol)
+        bf, bm = _brute_flags_interp(gf, gc, Bf, Bc, q, frames, lo, hi, tol)
+        assert np.array_equal(fl, bf) and np.array_equal(m, bm)
+        if lo <= hi:
+            assert bf.any() and not bf.all()
+
+
+def test_flags_interp_same_grid_equals_flags(oracle):
+    O = oracle
+    rng = np.random.default_rng(5)
+    g = O.Grid(12, 9, 1024.0, 2048.0, 0.0, 0.0)
+    K = 3
+    B = -rng.uniform(-5.0, 100.0, (9, 12))
+    h = np.maximum(0.0, rng.normal(0, 0.2, B.shape) - B)
+    q = [h, rng.normal(0, 1, h.shape), rng.normal(0, 1, h.shape)]
+    frames = rng.normal(0, 0.01, (K + 1, 3, 9, 12))
+    p = O.Params()
+    a = O.flag(g, p, O.NONLINEAR, B, q[0], q[1], q[2], frames, K, 0, K, 0.01)
+    b = O.flag_interp(g, p, O.NONLINEAR, B, q[0], q[1], q[2], g, B, frames, K, 0, K, 0.01)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_run_with_coarse_adjoint(oracle):
+    """The driver with the adjoint on a grid of half the resolution: the
+    snapshots come from the adjoint run on that grid, the flags at t0
+    interpolate them, and the coarse adjoint flags nearly the same region as
+    the adjoint on the forward grid."""
+    O = oracle
+    n = 64
+    b = I.basin(n, 3)
+    bc = I.basin(n // 2, 3)
+    g, gc = _grid2d(O, b), _grid2d(O, bc)
+    p = O.Params()
+    tgt = (b.target[0], b.target[1], 60e3)
+    K, tf = 6, 3600.0
+    r = O.run(g, p, O.NONLINEAR, b.B, b.eta0, tgt, 0.0, 1800.0, tf, K, 1e-4, flag_every=2,
+              adj_grid=gc, adj_B=bc.B)
+    assert r.status == 0 and r.frames.shape == (K + 1, 3, n // 2, n // 2)
+    phi = O.target(gc, p, bc.B, *tgt, O.GAUSS)
+    assert np.array_equal(r.frames[0, 0], phi)
+    q0 = O.init_state(g, p, O.NONLINEAR, b.B, b.eta0)
+    lo, hi = O.window(0.0, 0.0, 1800.0, tf, K)
+    fl0, _ = O.flag_interp(g, p, O.NONLINEAR, b.B, q0[0], q0[1], q0[2], gc, bc.B, r.frames, K, lo, hi, 1e-4)
+    assert np.array_equal(r.flags_at[0], fl0)
+    rf = O.run(g, p, O.NONLINEAR, b.B, b.eta0, tgt, 0.0, 1800.0, tf, K, 1e-4, flag_every=2)
+    both = (r.flag_acc & rf.flag_acc).sum()
+    assert both >= 0.8 * max(r.flag_acc.sum(), rf.flag_acc.sum())
