@@ -290,6 +290,17 @@ def secondary(S, torch, I, np, f64):
     fbytes = n * n * (32 + 24 * W + 1 + 1 + 1 + 16)
     out["flag_512_w34_us"] = t * 1e6
     out["flag_512_w34_GBs"] = fbytes / t / 1e9
+    # the same pass with the snapshots on a 256^2 adjoint grid (bilinear
+    # interpolation at every cell and snapshot)
+    nc = n // 2
+    bc = I.basin(nc, 3)
+    gcs = S.Grid(nc, nc, bc.grid.dx, bc.grid.dy)
+    Bc = torch.tensor(bc.B, **f64)
+    framesc = torch.randn(K + 1, 3, nc, nc, **f64) * 1e-3
+    t = _time_events(torch, lambda: S.adj_flag_interp(g, p, B, q, gcs, Bc, framesc, K, 30, 63, 1e-4, fl, None,
+                                                      acc, macc), 100)
+    out["flag_interp_512_from_256_w34_us"] = t * 1e6
+    out["flag_interp_512_from_256_w34_cells_per_s"] = n * n / t
     # the 4096^2 grid (~0.9 GB working set, beyond the 256 MB last-level cache)
     n = 4096
     b = I.basin(n, 2)
@@ -362,6 +373,30 @@ def run_bench(S, torch, I, np, f64):
                                            "adjoint": adj_counts, "surface": srf_counts,
                                            "adjoint_mean": sum(adj_counts) / len(adj_counts),
                                            "surface_mean": sum(srf_counts) / len(srf_counts)}}
+    # the 512^2 adjoint-flagging run with the adjoint on a 256^2 grid
+    n, nc, K, ts, tf, tol = 512, 256, 64, 3600.0, 7200.0, 1e-4
+    b, bc = I.basin(n, 3), I.basin(nc, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    gc = S.Grid(nc, nc, bc.grid.dx, bc.grid.dy)
+    prm = S.Params()
+    B, E, Bc = torch.tensor(b.B, **f64), torch.tensor(b.eta0, **f64), torch.tensor(bc.B, **f64)
+    frames = torch.zeros(K + 1, 3, nc, nc, **f64)
+    q = [torch.zeros(n, n, **f64) for _ in range(3)]
+    acc = torch.zeros(n, n, dtype=torch.int8, device=B.device)
+    macc = torch.zeros(n, n, **f64)
+    pb = S.make_problem(g, prm, B, E, b.target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc,
+                        adj_grid=gc, adj_B=Bc)
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
+    S.swe_run(pb, ws)
+    acc.zero_(); macc.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = S.swe_run(pb, ws)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    out["run2d_512_adjoint256"] = {"s": round(el, 4), "adjoint_steps": r.n_adj_steps, "adjoint_cells": nc * nc,
+                                   "forward_steps": r.n_fwd_steps, "flag_passes": r.n_flag_calls,
+                                   "flagged_cells": int(acc.sum().item())}
     return out
 
 
