@@ -388,6 +388,56 @@ SWE_API swe_status swe_advance_flagged(const swe_grid *grid, const swe_params *p
                                        const swe_flagging *fl, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Regridding: flagged cells -> rectangular boxes -> refined patches for the
+ * batched level (the clustering step that follows flagging in block-
+ * structured AMR, Sec. 1).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t i_lo, j_lo;     /* lower-left cell of the box on the flagged grid */
+    int32_t nx, ny;         /* box size in cells */
+} swe_box;
+
+/*
+ * swe_cluster - (host) point clustering of the non-zero cells of flags
+ * (ny rows of pitch bytes) into disjoint boxes by the signature method of
+ * Berger and Rigoutsos.  Recursively, starting from the whole grid:
+ *   1. shrink the box to the bounding box of its flagged cells (none: drop it);
+ *   2. if n_flagged >= efficiency * area and both sides <= max_side, keep it;
+ *   3. if it is efficient enough but too large, bisect the first side
+ *      (x before y) longer than max_side at len/2;
+ *   4. otherwise cut at a hole: a zero in the column (x) or row (y) signature,
+ *      cutting before that column/row at c in [1, len-1]; among holes the
+ *      one with the smallest |2c - len|, then x before y, then smaller c;
+ *   5. else at the strongest inflection of a signature: with the Laplacian
+ *      L[k] = S[k+1] - 2 S[k] + S[k-1] (1 <= k <= len-2), a cut at c = k+1
+ *      where L[k] L[k+1] < 0, min_side <= c <= len - min_side, strength
+ *      |L[k+1] - L[k]|; the strongest, then the smallest |2c - len|, then x
+ *      before y, then smaller c;
+ *   6. else bisect the longer side (x if equal) at len/2 if both halves have
+ *      >= min_side cells, else the other side; if neither, keep the box.
+ * The lower part is processed before the upper.  Returns the number of boxes
+ * (writing at most max_boxes of them), or a negative swe_status
+ * (SWE_E_INVAL: null pointers, sizes < 1, efficiency outside (0, 1],
+ * min_side < 1, max_side < 2 min_side).
+ */
+SWE_API int32_t swe_cluster(const int8_t *flags, int32_t nx, int32_t ny, int32_t pitch, double efficiency,
+                            int32_t min_side, int32_t max_side, swe_box *boxes, int32_t max_boxes);
+
+/*
+ * swe_prolong - fill refined patches from the coarse grid by piecewise-
+ * constant injection: fine cell (i, j) of patch k (the box boxes[k] refined
+ * by `ratio`, stored as described by patches[k], pitch = patches[k].nx) takes
+ * the values of coarse cell (i_lo + i / ratio, j_lo + j / ratio), for the
+ * three state planes and the bottom (a parent index outside the grid is
+ * clamped to it).  Conserves mass and keeps a lake at rest at rest.  boxes and patches are device arrays of n entries; out_B / out_q
+ * are the level's planes.  Enqueue only.  SWE_E_INVAL: null pointers,
+ * n < 1, ratio < 1.
+ */
+SWE_API swe_status swe_prolong(const swe_grid *grid, const double *B, swe_fields q, const swe_box *boxes,
+                               const swe_patch *patches, int32_t n, int32_t ratio, double *out_B,
+                               swe_fields out_q, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving: scenarios (a tsunami source on a grid, with its target region and
  * time window) arriving over time, run through the two-phase driver with
  * several in flight at once.

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswe.so")
 STAMP = LIB + ".sources"      # hash of the sources the library was built from
-SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip", "swe_serve.hip"]
+SOURCES = ["swe_kernels.hip", "swe_abi.hip", "swe_level.hip", "swe_serve.hip", "swe_regrid.hip"]
 
 # binary64 without contraction (results are defined op by op); packed FP32
 # instructions disabled.

@@ -108,7 +108,7 @@ def lib():
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
                      "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
-                     "swe_serve", "swe_surface_flag", "adj_flag_interp"):
+                     "swe_serve", "swe_surface_flag", "adj_flag_interp", "swe_cluster", "swe_prolong"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_serve_footprint.restype = C.c_size_t
@@ -463,6 +463,33 @@ def level_advance(level: Level, prm: Params, B, a, b, ctl, n_steps: int, persist
     _check(lib().swe_level_advance(C.byref(level.c), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                                    _ptr(ctl), C.c_int32(n_steps), C.c_int32(persistent),
                                    _stream(stream)))
+
+
+class swe_box(C.Structure):
+    _fields_ = [("i_lo", C.c_int32), ("j_lo", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32)]
+
+
+def cluster(flags, efficiency=0.7, min_side=4, max_side=32):
+    """Host clustering of the non-zero cells of flags (numpy int8 (ny, nx)) into
+    boxes [(i_lo, j_lo, nx, ny), ...] (see swe_cluster)."""
+    import numpy as np
+    f = np.ascontiguousarray(flags, dtype=np.int8)
+    ny, nx = f.shape
+    args = (f.ctypes.data_as(C.c_void_p), C.c_int32(nx), C.c_int32(ny), C.c_int32(nx), C.c_double(efficiency),
+            C.c_int32(min_side), C.c_int32(max_side))
+    n = lib().swe_cluster(*args, None, C.c_int32(0))
+    if n < 0:
+        _check(n)
+    out = (swe_box * max(n, 1))()
+    n2 = lib().swe_cluster(*args, out, C.c_int32(n))
+    if n2 < 0:
+        _check(n2)
+    return [(b.i_lo, b.j_lo, b.nx, b.ny) for b in out[:n]]
+
+
+def prolong(grid: Grid, B, q, boxes_dev, patches_dev, n, ratio, out_B, out_q, stream=None):
+    _check(lib().swe_prolong(C.byref(grid.c()), _ptr(B), fields(q), _ptr(boxes_dev), _ptr(patches_dev),
+                             C.c_int32(n), C.c_int32(ratio), _ptr(out_B), fields(out_q), _stream(stream)))
 
 
 class swe_tune_entry(C.Structure):

@@ -50,7 +50,7 @@ def test_every_declared_symbol_is_exported(S):
 def _struct_classes(S):
     return [S.swe_grid, S.swe_params, S.swe_fields, S.swe_problem, S.swe_result, S.swe_ctl_state,
             S.swe_ctl, S.swe_patch, S.swe_level, S.swe_tune_entry, S.swe_flagging, S.swe_request,
-            S.swe_request_stats, S.swe_serve_config]
+            S.swe_request_stats, S.swe_serve_config, S.swe_box]
 
 
 def test_ctypes_mirrors_match_the_header(S, tmp_path):
