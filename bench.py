@@ -358,6 +358,8 @@ def run_bench(S, torch, I, np, f64):
         S.swe_run(pw, ws)
         adj_counts = flags_at.view(K + 1, -1).sum(dim=1, dtype=torch.int64).cpu().tolist()
         srf_counts = sflags.view(K + 1, -1).sum(dim=1, dtype=torch.int64).cpu().tolist()
+        if ny > 1:
+            out["regrid_512"] = regrid_bench(S, torch, np, g, B, q, flags_at[K], f64)
         pb = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc)
         acc.zero_(); macc.zero_()
         torch.cuda.synchronize()
@@ -398,6 +400,45 @@ def run_bench(S, torch, I, np, f64):
                                    "forward_steps": r.n_fwd_steps, "flag_passes": r.n_flag_calls,
                                    "flagged_cells": int(acc.sum().item())}
     return out
+
+
+def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
+    """One regrid of the adaptive loop on the 512^2 run's final adjoint flags:
+    host clustering, injection of the coarse state into the 2x refined
+    patches, and steps of the refined level."""
+    fl = flags.cpu().numpy()
+    t = time.perf_counter()
+    boxes = S.cluster(fl, 0.7, 4, 32)
+    t_cluster = time.perf_counter() - t
+    if not boxes:
+        return {"boxes": 0}
+    nxp = [nx * ratio for (_, _, nx, _) in boxes]
+    nyp = [ny * ratio for (_, _, _, ny) in boxes]
+    tab, ncell = S.patch_table(nxp, nyp, [g.dx / ratio] * len(boxes))
+    lvl = S.Level(tab, S.SCHED_PACKED)
+    box_t = torch.tensor(np.array(boxes, np.int32), device=B.device)
+    Bp = torch.empty(ncell, **f64)
+    qa = [torch.empty(ncell, **f64) for _ in range(3)]
+    qb = [torch.empty(ncell, **f64) for _ in range(3)]
+    t_prolong = _time_events(torch, lambda: S.prolong(g, B, q, box_t, lvl.patches_t, len(boxes), ratio, Bp, qa), 20)
+    spd = torch.zeros(1, dtype=torch.int64, device=B.device)
+    S.swe_max_speed(S.Grid(int(g.nx), int(g.ny), g.dx / ratio, g.dy / ratio), S.Params(), B, q, 0, spd)
+    dt0 = S.Params().cfl_desired / float(spd.view(torch.float64).item())
+    ctl = S.new_ctl()
+    S.swe_ctl_set(ctl, 0.0, dt0, 1.0e300, 0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    S.level_advance(lvl, S.Params(), Bp, qa, qb, ctl, n_steps, 0)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    c = S.read_ctl(ctl)
+    area = sum(nx * ny for (_, _, nx, ny) in boxes)
+    return {"flagged_cells": int(fl.sum()), "boxes": len(boxes), "box_efficiency": round(int(fl.sum()) / area, 3),
+            "cluster_ms": round(t_cluster * 1e3, 3), "refined_cells": ncell, "prolong_us": round(t_prolong * 1e6, 2),
+            "level_steps": n_steps, "level_accepted": c.n_accepted, "level_us_per_step": round(ms * 1e3 / n_steps, 2),
+            "level_cell_updates_per_s": ncell * c.n_accepted / (ms * 1e-3)}
 
 
 def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
