@@ -416,6 +416,7 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
     nyp = [ny * ratio for (_, _, _, ny) in boxes]
     tab, ncell = S.patch_table(nxp, nyp, [g.dx / ratio] * len(boxes))
     lvl = S.Level(tab, S.SCHED_PACKED)
+    lvl_c = S.Level(tab, S.SCHED_PACKED, chunk_rows=8)
     box_t = torch.tensor(np.array(boxes, np.int32), device=B.device)
     Bp = torch.empty(ncell, **f64)
     qa = [torch.empty(ncell, **f64) for _ in range(3)]
@@ -424,20 +425,29 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
     spd = torch.zeros(1, dtype=torch.int64, device=B.device)
     S.swe_max_speed(S.Grid(int(g.nx), int(g.ny), g.dx / ratio, g.dy / ratio), S.Params(), B, q, 0, spd)
     dt0 = S.Params().cfl_desired / float(spd.view(torch.float64).item())
-    ctl = S.new_ctl()
-    S.swe_ctl_set(ctl, 0.0, dt0, 1.0e300, 0)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    S.level_advance(lvl, S.Params(), Bp, qa, qb, ctl, n_steps, 0)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    c = S.read_ctl(ctl)
+    init = [x.clone() for x in qa]
+
+    def timed(level):
+        for c_ in range(3):
+            qa[c_].copy_(init[c_])
+        ctl = S.new_ctl()
+        S.swe_ctl_set(ctl, 0.0, dt0, 1.0e300, 0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        S.level_advance(level, S.Params(), Bp, qa, qb, ctl, n_steps, 0)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), S.read_ctl(ctl)
+
+    ms_whole, _ = timed(lvl)
+    ms, c = timed(lvl_c)
     area = sum(nx * ny for (_, _, nx, ny) in boxes)
     return {"flagged_cells": int(fl.sum()), "boxes": len(boxes), "box_efficiency": round(int(fl.sum()) / area, 3),
             "cluster_ms": round(t_cluster * 1e3, 3), "refined_cells": ncell, "prolong_us": round(t_prolong * 1e6, 2),
-            "level_steps": n_steps, "level_accepted": c.n_accepted, "level_us_per_step": round(ms * 1e3 / n_steps, 2),
+            "level_steps": n_steps, "level_accepted": c.n_accepted,
+            "level_us_per_step_whole_patches": round(ms_whole * 1e3 / n_steps, 2),
+            "level_us_per_step": round(ms * 1e3 / n_steps, 2), "level_chunk_rows": 8,
             "level_cell_updates_per_s": ncell * c.n_accepted / (ms * 1e-3)}
 
 
@@ -460,15 +470,17 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
         S.swe_init(g, prm, B[o:o + n], eta[o:o + n], q)
         S.swe_max_speed(g, prm, B[o:o + n], q, 0, spd)
     dt0 = prm.cfl_desired / float(spd.view(torch.float64).item())
-    levels = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED)]
+    levels = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED),
+              S.Level(tab, S.SCHED_PACKED, chunk_rows=16)]
     wa = [torch.empty(ncell, **f64) for _ in range(3)]
     wb = [torch.empty(ncell, **f64) for _ in range(3)]
     ref = [torch.empty(ncell, **f64) for _ in range(3)]
     ctl = S.new_ctl()
     mism = torch.zeros(1, dtype=torch.int32, device=B.device)
     entries, best = S.level_tune(levels, prm, B, init, wa, wb, ref, ctl, mism, dt0, 10, ncell)
-    names = {(0, 0): "strip/launch-per-step", (0, 1): "strip/persistent",
-             (1, 0): "packed/launch-per-step", (1, 1): "packed/persistent"}
+    lnames = ["strip", "packed", "packed-16-row-chunks"]
+    names = {(l, pm): f"{lnames[l]}/{'persistent' if pm else 'launch-per-step'}"
+             for l in range(len(levels)) for pm in (0, 1)}
     lv, pers, _ = entries[best]
     # timed run of the chosen schedule
     for c in range(3):
@@ -507,10 +519,9 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
     torch.cuda.synchronize()
     per_patch = _time_events(torch, graph.replay, 5)
     return {"level_patches": n_patches, "level_cells": ncell,
-            "level_candidates_us_per_step": {names[(l, p)]: round(u, 2) for l, p, u in entries},
+            "level_candidates_us_per_step": {names[(l, p)]: round(u, 2) for l, p, u in entries if u >= 0},
             "level_schedule": names[(lv, pers)],
-            "level_lane_occupancy": {"strip": round(levels[0].lane_occupancy, 3),
-                                     "packed": round(levels[1].lane_occupancy, 3)},
+            "level_lane_occupancy": {lnames[k]: round(levels[k].lane_occupancy, 3) for k in range(len(levels))},
             "level_steps": n_steps, "level_accepted": c.n_accepted,
             "level_cell_updates_per_s": best_rate,
             "level_ms_per_step": ms / n_steps,

@@ -264,28 +264,34 @@ typedef enum {
  * swe_level_schedule - (host) build the wavefront schedule of a level.
  * A pass is one wavefront's work: up to 64 lanes, each lane a column of one
  * patch strip (the strip's columns plus 2 ghost columns each side); all its
- * patches are marched over `pass_rows` rows.  A job is a run of passes done by
- * one wavefront; every patch lies within one job.
+ * patches are marched over rows pass_row0 .. pass_row0 + pass_rows - 1.  A job
+ * is a run of passes done by one wavefront.  With chunk_rows > 0 every pass
+ * taller than chunk_rows is cut into passes of at most chunk_rows rows (each
+ * its own job: more wavefronts for small levels, at the cost of the chunks'
+ * halo rows); with chunk_rows = 0 a pass covers its patches' full height and
+ * every patch lies within one job.
  *   lanes:     n_passes*64 int64, lane = (patch << 32) | (role << 16) | (col + 32768),
  *              role bit 0: output column, bit 1: its west edge counts for the
  *              Courant number; -1 for an idle lane
- *   pass_rows: n_passes int32;  job_pass: n_jobs+1 int32 (passes of job j are
- *              job_pass[j] .. job_pass[j+1]-1)
+ *   pass_rows, pass_row0: n_passes int32;  job_pass: n_jobs+1 int32 (passes of
+ *              job j are job_pass[j] .. job_pass[j+1]-1)
  * Call with null outputs to get the sizes.  Returns n_passes (>= 0) and sets
  * *n_jobs, or a negative swe_status.  patches: host array.
  */
-SWE_API int32_t swe_level_schedule(const swe_patch *patches, int32_t n_patches, int32_t kind,
-                                   int64_t *lanes, int32_t *pass_rows, int32_t *job_pass,
+SWE_API int32_t swe_level_schedule(const swe_patch *patches, int32_t n_patches, int32_t kind, int32_t chunk_rows,
+                                   int64_t *lanes, int32_t *pass_rows, int32_t *pass_row0, int32_t *job_pass,
                                    int32_t *n_jobs);
 
 /* A level on the device. */
 typedef struct {
-    int32_t n_patches, n_passes, n_jobs, reserved;
+    int32_t n_patches, n_passes, n_jobs;
+    int32_t chunk_rows;         /* the schedule's chunk_rows (0: whole patches) */
     const swe_patch *patches;   /* device table */
     const int64_t *lanes;       /* device, from swe_level_schedule */
     const int32_t *pass_rows;   /* device */
     const int32_t *job_pass;    /* device */
     uint32_t *sync;             /* device, 4 words zeroed once by the caller (persistent mode) */
+    const int32_t *pass_row0;   /* device, first row of each pass (NULL: all 0) */
 } swe_level;
 
 /*
@@ -298,8 +304,10 @@ typedef struct {
  * a barrier that does not open within a bounded spin sets sync[2] to nonzero
  * and the launch ends early (the caller checks sync[2]; the state is then
  * not a valid result).  Each patch is owned by one wavefront, so patches never
- * exchange data within a launch.  State in a (cur = 0) / b (cur = 1); B: bottom
- * planes of the level.  Enqueue only.
+ * exchange data within a launch; a level cut into row chunks (chunk_rows > 0)
+ * is therefore refused in persistent mode (SWE_E_INVAL): its chunks read
+ * halo rows that other wavefronts wrote in the previous attempt.  State in
+ * a (cur = 0) / b (cur = 1); B: bottom planes of the level.  Enqueue only.
  */
 SWE_API swe_status swe_level_advance(const swe_level *level, const swe_params *prm, const double *B,
                                      swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_steps,
@@ -319,7 +327,8 @@ typedef struct {
  * n_trial attempts from dt with the control rule, time them with HIP events,
  * and compare the resulting state bit for bit with the first candidate's (kept
  * in `ref`).  Writes 2*n_levels entries to `out` (host) and the index of the
- * fastest into *best.  Returns SWE_E_HIP if two candidates disagree in any
+ * fastest into *best; the persistent mode of a level cut into row chunks is
+ * not run (its entry has us_per_attempt = -1).  Returns SWE_E_HIP if two candidates disagree in any
  * bit (*mismatch, device int32, receives the count).  Synchronises `stream`.
  */
 SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, const swe_params *prm,

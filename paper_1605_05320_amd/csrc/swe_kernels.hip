@@ -303,8 +303,9 @@ __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L,
     G.bc[0] = pt.bc[0]; G.bc[1] = pt.bc[1]; G.bc[2] = pt.bc[2]; G.bc[3] = pt.bc[3];
     G.base = pt.offset;
     const int rows = L.pass_rows[pass];
-    march<M>(P, G, lane, col, 0, pt.ny, rows, (role & 1) != 0, (role & 2) != 0, pt.dx, pt.dy, cfl,
-             nclamp, nbad);
+    const int row0 = L.pass_row0 ? L.pass_row0[pass] : 0;
+    march<M>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
+             pt.dx, pt.dy, cfl, nclamp, nbad);
 }
 
 // One level step attempt: one wavefront per pass.

@@ -25,6 +25,7 @@ struct Pass {
     std::vector<Seg> segs;
     int used = 0;
     int rows = 0;
+    int row0 = 0;
 };
 
 long long lane_code(int patch, int role, int col)
@@ -51,12 +52,13 @@ void fill_lanes(const Pass &p, long long *out)
 
 extern "C" {
 
-int32_t swe_level_schedule(const swe_patch *patches, int32_t n, int32_t kind, int64_t *lanes,
-                           int32_t *pass_rows, int32_t *job_pass, int32_t *n_jobs_out)
+int32_t swe_level_schedule(const swe_patch *patches, int32_t n, int32_t kind, int32_t chunk_rows, int64_t *lanes,
+                           int32_t *pass_rows, int32_t *pass_row0, int32_t *job_pass, int32_t *n_jobs_out)
 {
     using swe::fail;
     if (!patches || n < 1 || !n_jobs_out) return fail(SWE_E_INVAL, "need patches, n >= 1 and n_jobs");
     if (kind != SWE_SCHED_STRIP && kind != SWE_SCHED_PACKED) return fail(SWE_E_INVAL, "unknown schedule kind");
+    if (chunk_rows < 0) return fail(SWE_E_INVAL, "chunk_rows must be >= 0");
     for (int p = 0; p < n; ++p)
         if (patches[p].nx < 2 || patches[p].ny < 2 || patches[p].offset < 0 || !(patches[p].dx > 0.0) ||
             !(patches[p].dy > 0.0))
@@ -124,17 +126,40 @@ int32_t swe_level_schedule(const swe_patch *patches, int32_t n, int32_t kind, in
             return ca > cb;
         });
     }
+    if (chunk_rows > 0) {
+        // cut tall passes into row chunks, each chunk a job of its own
+        std::vector<std::vector<Pass>> cut;
+        for (auto &j : jobs)
+            for (const Pass &ps : j) {
+                if (ps.rows <= chunk_rows) {
+                    cut.push_back({ps});
+                    continue;
+                }
+                for (int r0 = 0; r0 < ps.rows; r0 += chunk_rows) {
+                    Pass c = ps;
+                    c.row0 = r0;
+                    c.rows = std::min(chunk_rows, ps.rows - r0);
+                    cut.push_back({c});
+                }
+            }
+        std::stable_sort(cut.begin(), cut.end(), [](const std::vector<Pass> &a, const std::vector<Pass> &b) {
+            return a[0].rows > b[0].rows;
+        });
+        jobs.swap(cut);
+    }
     int npass = 0;
     for (auto &j : jobs) npass += (int)j.size();
     *n_jobs_out = (int32_t)jobs.size();
-    if (!lanes && !pass_rows && !job_pass) return npass;
-    if (!lanes || !pass_rows || !job_pass) return fail(SWE_E_INVAL, "lanes, pass_rows and job_pass go together");
+    if (!lanes && !pass_rows && !pass_row0 && !job_pass) return npass;
+    if (!lanes || !pass_rows || !pass_row0 || !job_pass)
+        return fail(SWE_E_INVAL, "lanes, pass_rows, pass_row0 and job_pass go together");
     int q = 0;
     for (size_t j = 0; j < jobs.size(); ++j) {
         job_pass[j] = q;
         for (const Pass &ps : jobs[j]) {
             fill_lanes(ps, (long long *)lanes + (size_t)q * swe::WAVE);
             pass_rows[q] = ps.rows;
+            pass_row0[q] = ps.row0;
             ++q;
         }
     }
@@ -156,6 +181,8 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
         !(prm->cfl_max >= prm->cfl_desired))
         return fail(SWE_E_INVAL, "bad parameters (nonlinear model, order, transverse, 0 < cfl_desired <= cfl_max)");
     if (persistent && !L->sync) return fail(SWE_E_INVAL, "persistent mode needs the sync words");
+    if (persistent && L->chunk_rows > 0)
+        return fail(SWE_E_INVAL, "persistent mode needs whole-patch jobs (chunk_rows = 0)");
     if (n_steps == 0) return SWE_OK;
 
     swe::KParams k;
@@ -181,6 +208,7 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
     la.pass_rows = L->pass_rows;
     la.job_pass = L->job_pass;
     la.sync = L->sync;
+    la.pass_row0 = L->pass_row0;
     hipStream_t s = (hipStream_t)stream;
     if (!persistent) {
         for (int n = 0; n < n_steps; ++n) {
@@ -226,6 +254,14 @@ swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, cons
     int nout = 0;
     bool have_ref = false;
     auto run_candidate = [&](int k, int pers) -> swe_status {
+        if (pers && levels[k]->chunk_rows > 0) {
+            // chunked levels only run one launch per attempt
+            out[nout].level = k;
+            out[nout].persistent = pers;
+            out[nout].us_per_attempt = -1.0;
+            ++nout;
+            return SWE_OK;
+        }
         swe_status st;
         const double *src[3] = {init.f0, init.f1, init.f2};
         double *dst[3] = {work_a.f0, work_a.f1, work_a.f2};

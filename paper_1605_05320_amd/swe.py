@@ -398,8 +398,9 @@ class swe_patch(C.Structure):
 
 class swe_level(C.Structure):
     _fields_ = [("n_patches", C.c_int32), ("n_passes", C.c_int32), ("n_jobs", C.c_int32),
-                ("reserved", C.c_int32), ("patches", C.c_void_p), ("lanes", C.c_void_p),
-                ("pass_rows", C.c_void_p), ("job_pass", C.c_void_p), ("sync", C.c_void_p)]
+                ("chunk_rows", C.c_int32), ("patches", C.c_void_p), ("lanes", C.c_void_p),
+                ("pass_rows", C.c_void_p), ("job_pass", C.c_void_p), ("sync", C.c_void_p),
+                ("pass_row0", C.c_void_p)]
 
 
 def patch_table(nx, ny, dx, dy=None, bc=(BC_WALL,) * 4):
@@ -418,43 +419,47 @@ def patch_table(nx, ny, dx, dy=None, bc=(BC_WALL,) * 4):
     return tab, off
 
 
-def level_schedule(tab, kind=SCHED_PACKED):
+def level_schedule(tab, kind=SCHED_PACKED, chunk_rows=0):
     """Host schedule: returns (lanes int64[n_passes*64], pass_rows int32[n_passes],
-    job_pass int32[n_jobs+1]) as numpy arrays."""
+    job_pass int32[n_jobs+1], pass_row0 int32[n_passes]) as numpy arrays."""
     import numpy as np
     n = len(tab)
     nj = C.c_int32(0)
-    npass = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind), None, None, None, C.byref(nj))
+    npass = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind), C.c_int32(chunk_rows), None, None, None,
+                                     None, C.byref(nj))
     if npass < 0:
         _check(npass)
     lanes = np.empty(npass * 64, np.int64)
     rows = np.empty(npass, np.int32)
+    row0 = np.empty(npass, np.int32)
     jp = np.empty(nj.value + 1, np.int32)
-    r = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind),
+    r = lib().swe_level_schedule(tab, C.c_int32(n), C.c_int32(kind), C.c_int32(chunk_rows),
                                  lanes.ctypes.data_as(C.c_void_p), rows.ctypes.data_as(C.c_void_p),
-                                 jp.ctypes.data_as(C.c_void_p), C.byref(nj))
+                                 row0.ctypes.data_as(C.c_void_p), jp.ctypes.data_as(C.c_void_p), C.byref(nj))
     if r < 0:
         _check(r)
-    return lanes, rows, jp
+    return lanes, rows, jp, row0
 
 
 class Level:
     """A level's schedule and patch table on the device (tensors kept alive here)."""
 
-    def __init__(self, tab, kind=SCHED_PACKED, device="cuda"):
+    def __init__(self, tab, kind=SCHED_PACKED, device="cuda", chunk_rows=0):
         import numpy as np
         import torch
-        lanes, rows, jp = level_schedule(tab, kind)
+        lanes, rows, jp, row0 = level_schedule(tab, kind, chunk_rows)
         raw = np.frombuffer(bytes(tab), dtype=np.uint8)
         self.kind = kind
+        self.chunk_rows = chunk_rows
         self.patches_t = torch.tensor(raw, dtype=torch.uint8, device=device)
         self.lanes_t = torch.tensor(lanes, device=device)
         self.rows_t = torch.tensor(rows, device=device)
+        self.row0_t = torch.tensor(row0, device=device)
         self.jp_t = torch.tensor(jp, device=device)
         self.sync_t = torch.zeros(4, dtype=torch.int32, device=device)
-        self.c = swe_level(len(tab), len(rows), len(jp) - 1, 0, self.patches_t.data_ptr(),
+        self.c = swe_level(len(tab), len(rows), len(jp) - 1, chunk_rows, self.patches_t.data_ptr(),
                            self.lanes_t.data_ptr(), self.rows_t.data_ptr(), self.jp_t.data_ptr(),
-                           self.sync_t.data_ptr())
+                           self.sync_t.data_ptr(), self.row0_t.data_ptr())
         self.lane_occupancy = float((lanes >= 0).mean())
 
 

@@ -72,14 +72,15 @@ def to_arena(arrs):
     return np.concatenate([a.ravel() for a in arrs])
 
 
-@pytest.mark.parametrize("kind,persistent", [(0, 0), (1, 0), (1, 1), (0, 1)])
-def test_level_parity(oracle, S, setup, kind, persistent):
+@pytest.mark.parametrize("kind,persistent,chunk", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (1, 0, 16),
+                                                    (1, 0, 12), (0, 0, 9), (1, 0, 1)])
+def test_level_parity(oracle, S, setup, kind, persistent, chunk):
     ps, B, q, dt0 = setup
     n_steps = 7
     qc, t, dt, acc, rej = oracle_level(oracle, ps, B, q, 1.6 * dt0, n_steps)
     assert rej >= 1 and acc >= 1
     tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
-    lvl = S.Level(tab, kind)
+    lvl = S.Level(tab, kind, chunk_rows=chunk)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
     Bd = dev(to_arena(B))
     a = [dev(to_arena([qq[c] for qq in q])) for c in range(3)]
@@ -106,4 +107,15 @@ def test_level_parity(oracle, S, setup, kind, persistent):
             assert np.abs(g_ - r_).max() <= 1e-12 * max(scale, 1e-300), (k, comp)
             exact &= np.array_equal(got[comp][off:off + n], qc[k][comp].ravel())
         off += n
-    print(f"level kind={kind} persistent={persistent}: bit-exact={exact}")
+    print(f"level kind={kind} persistent={persistent} chunk={chunk}: bit-exact={exact}")
+
+
+def test_persistent_refuses_row_chunks(S, setup):
+    ps, B, q, dt0 = setup
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    lvl = S.Level(tab, 1, chunk_rows=16)
+    z = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    w = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
+    ctl = S.new_ctl()
+    with pytest.raises(S.SweError):
+        S.level_advance(lvl, S.Params(), z[0], z, w, ctl, 3, 1)
