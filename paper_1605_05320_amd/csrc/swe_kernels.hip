@@ -58,8 +58,9 @@ __device__ __forceinline__ void keep_qrow(const typename M::Cell &c, QRow &r)
     r.upd = M::updates(c);
 }
 
-// y-edge correction flux from a YPrev-style lower neighbour.
-template <class M>
+// y-edge correction flux from a YPrev-style lower neighbour (SUB: sub_edge
+// holds for e on every lane).
+template <class M, bool SUB>
 __device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const Edge &hi, const KParams &P,
                                           double nuy, double hnux,
                                           const double *t0, int ty0, const double *t1, int ty1,
@@ -73,41 +74,150 @@ __device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const 
         double cx[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int p = 0; p < M::NW; ++p) {
-            const bool upwind_lo = e.s[p] > 0.0;
             double uz[3];
+            if (SUB && p == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) uz[c] = upwind_lo ? lo.z[p][c] : hi.z[p][c];
-            double dd, du;
-            if (M::zc(p, 0) && M::zc(p, 1)) {
-                dd = e.z[p][0] * e.z[p][0] + e.z[p][1] * e.z[p][1];
-                du = uz[0] * e.z[p][0] + uz[1] * e.z[p][1];
-                if (M::zc(p, 2)) {
-                    dd = dd + e.z[p][2] * e.z[p][2];
-                    du = du + uz[2] * e.z[p][2];
-                }
+                for (int c = 0; c < 3; ++c) uz[c] = hi.z[p][c];
+                limited_wave<M, -1>(e, p, uz, nuy, cx);
+            } else if (SUB && p == M::NW - 1) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) uz[c] = lo.z[p][c];
+                limited_wave<M, 1>(e, p, uz, nuy, cx);
             } else {
-                dd = e.z[p][2] * e.z[p][2];
-                du = uz[2] * e.z[p][2];
-            }
-            if (dd == 0.0) continue;
-            double phi = mc_phi(du / dd);
-            double as = fabs(e.s[p]);
-            double a = 1.0 - nuy * as;
-            double w;
-            if (M::FWAVE)
-                w = e.s[p] > 0.0 ? a : (e.s[p] < 0.0 ? -a : 0.0);
-            else
-                w = as * a;
+                const bool upwind_lo = e.s[p] > 0.0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if (M::zc(p, c)) cx[c] = cx[c] + w * (phi * e.z[p][c]);
+                for (int c = 0; c < 3; ++c) uz[c] = upwind_lo ? lo.z[p][c] : hi.z[p][c];
+                limited_wave<M, 0>(e, p, uz, nuy, cx);
+            }
         }
         Gn[0] = 0.5 * cx[0]; Gn[1] = 0.5 * cx[1]; Gn[2] = 0.5 * cx[2];
     }
     to_phys(true, Gn, G);
     if (P.transverse)
-        transverse_gather<M>(e, true, hnux, t0, ty0 == E_WET, t1, ty1 == E_WET, t2, ty2 == E_WET,
-                             t3, ty3 == E_WET, G);
+        transverse_gather<M, SUB>(e, true, hnux, t0, ty0 == E_WET, t1, ty1 == E_WET, t2, ty2 == E_WET,
+                                  t3, ty3 == E_WET, G);
+}
+
+// Correction fluxes of row r: G(i, r + 1/2) of y-edge yN (whose lower
+// neighbour is yS) and F(i - 1/2, r) of x-edge xCur (limiter from lanes -1/+1,
+// transverse terms from the y-edges of columns i-1 (lane - 1) and i (own)).
+// SUB: sub_edge holds for yN and xCur on every lane.  Every lane of the
+// wavefront must call this (shuffles).
+template <class M, bool SUB>
+__device__ __forceinline__ void row_fluxes(const KParams &P, const Edge &yN, const YPrev &yS, const Edge &yNN,
+                                           const Edge &xCur, const XFl &xCurE, const Edge &xNext,
+                                           const XFl &xNextE, double nux, double nuy, double hnux, double hnuy,
+                                           double G_N[3], double F_W[3])
+{
+    g_tilde_r<M, SUB>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE.am, xCurE.t,
+                      xNext.ap, xNext.type, xNextE.am, xNextE.t, G_N);
+    F_W[0] = 0.0; F_W[1] = 0.0; F_W[2] = 0.0;
+    double Fn[3] = {0.0, 0.0, 0.0};
+    if (P.order == 2) correction_lanes<M, SUB>(xCur, nux, Fn);
+    double yS_ap_W[3], yN_am_W[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        yS_ap_W[c] = from_lo(yS.ap[c]);
+        yN_am_W[c] = from_lo(yN.am[c]);
+    }
+    int yS_t_W = from_lo(yS.type), yN_t_W = from_lo(yN.type);
+    if (xCur.type == E_WET) {
+        to_phys(false, Fn, F_W);
+        if (P.transverse)
+            transverse_gather<M, SUB>(xCur, false, hnuy, yS_ap_W, yS_t_W == E_WET, yN_am_W,
+                                      yN_t_W == E_WET, yS.ap, yS.type == E_WET, yN.am,
+                                      yN.type == E_WET, F_W);
+    }
+}
+
+// What a marching wavefront carries from row to row.
+template <class M>
+struct Window {
+    QRow qC;                 // row r (being updated)
+    typename M::Cell cD, cE; // rows r + 1, r + 2
+    YPrev yS;                // y-edge r - 1/2
+    Edge yN, xCur;           // y-edge r + 1/2, x-edge of row r
+    XFl xCurE;               // its east neighbour's A-dQ
+    Edge yNN, xNext;         // y-edge r + 3/2, x-edge of row r + 1
+    double G_S[3];           // G of edge r - 1/2
+    RawCell rE;              // stored values of row r + 3, loaded one row ahead
+    double smx, smy;         // largest |s| of the counted x- and y-edges
+};
+
+// Row r, first part: row r + 2's cell data and the waves of the row's two
+// new edges (y-edge r + 3/2, x-edge (i - 1/2, r + 1)).
+template <class M>
+__device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int i, int r, Window<M> &W)
+{
+    W.cE = M::cell(P, W.rE);
+    W.rE = M::raw(P, G, i, r + 3);                 // in flight during this row
+    M::waves(W.cD, W.cE, true, P, W.yNN);
+    typename M::Cell lD = M::lo_cell(W.cD);
+    M::waves(lD, W.cD, false, P, W.xNext);
+}
+
+// Row r, second part: fluctuations of the new edges, correction fluxes,
+// update and store of row r, then the window moves down one row.  SUB_NEW:
+// sub_edge holds for the new edges on every lane; SUB: for yN and xCur.
+template <class M, bool SUB_NEW, bool SUB>
+__device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i, int r, bool row_ok, bool core,
+                                           double nux, double nuy, double hnux, double hnuy, Window<M> &W,
+                                           int &nclamp, int &nbad)
+{
+    M::template fluct<SUB_NEW>(W.yNN, true);
+    M::template fluct<SUB_NEW>(W.xNext, false);
+    XFl xNextE;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xNextE.am[c] = from_hi(W.xNext.am[c]);
+    xNextE.t = from_hi(W.xNext.type);
+
+    double G_N[3], F_W[3];
+    row_fluxes<M, SUB>(P, W.yN, W.yS, W.yNN, W.xCur, W.xCurE, W.xNext, xNextE, nux, nuy, hnux, hnuy, G_N, F_W);
+    double F_E[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F_E[c] = from_hi(F_W[c]);
+
+    if (core && row_ok) {
+        double o[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double qv = W.qC.q[c];
+            if (W.qC.upd) {
+                qv = qv - nux * (W.xCur.ap[c] + W.xCurE.am[c]);
+                qv = qv - nuy * (W.yS.ap[c] + W.yN.am[c]);
+                qv = qv - nux * (F_E[c] - F_W[c]);
+                qv = qv - nuy * (G_N[c] - W.G_S[c]);
+            }
+            o[c] = qv;
+        }
+        if (M::DRYFIX) {
+            // nonlinear dry-cell fix
+            if (!(o[0] > P.dry_tol)) { o[1] = 0.0; o[2] = 0.0; }
+            if (o[0] < 0.0) { o[0] = 0.0; ++nclamp; }
+        }
+        if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) ++nbad;
+        size_t k = (size_t)(G.base + (long long)r * G.pitch + i);
+        P.out0[k] = o[0];
+        P.out1[k] = o[1];
+        P.out2[k] = o[2];
+    }
+    if (row_ok) {
+#pragma unroll
+        for (int p = 0; p < M::NW; ++p) {
+            W.smx = fmax_(W.smx, fabs(W.xCur.s[p]));
+            W.smy = fmax_(W.smy, fabs(W.yN.s[p]));
+        }
+    }
+
+    // move the window down one row, keeping only what is still needed
+    keep_yprev<M>(W.yN, W.yS);
+    W.yN = W.yNN;
+    W.xCur = W.xNext;
+    W.xCurE = xNextE;
+    keep_qrow<M>(W.cD, W.qC);
+    W.cD = W.cE;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) W.G_S[c] = G_N[c];
 }
 
 // The marching step of one wavefront: lane `lane` holds column i of the grid
@@ -115,138 +225,75 @@ __device__ __forceinline__ void g_tilde_r(const Edge &e, const YPrev &lo, const 
 // runs to jend (uniform over the wavefront), rows from j1 on are computed but
 // neither stored nor counted.  core: the lane's cell is an output cell;
 // xedge_in: its west edge counts for the Courant number.
+//
+// While every lane's edges have s_1 < 0 < s_NW (or are dry) - the case
+// everywhere in subcritical flow - rows run the forms that know those signs
+// (same values); from the first row where that fails the rest of the march
+// runs the general forms.  The Courant number is nu max|s|, which equals the
+// largest nu|s| exactly (rounding is monotonic).
 template <class M>
 __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
                                       int jend, bool core, bool xedge_in, double dx, double dy,
                                       double &cfl, int &nclamp, int &nbad)
 {
+    (void)lane;
     const double nux = P.dt / dx, nuy = P.dt / dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
     using Cell = typename M::Cell;
-    QRow qC;                 // row r (being updated)
-    Cell cD;                 // row r + 1
-    YPrev yS;                // y-edge r - 1/2
-    Edge yN, xCur;           // y-edge r + 1/2, x-edge of row r
-    XFl xCurE;               // its east neighbour's A-dQ
-    double G_S[3];           // G of edge r - 1/2
-    RawCell rE;              // stored values of row r + 2, loaded one row ahead
+    Window<M> W;
+    W.smx = 0.0;
+    W.smy = 0.0;
     {
         Cell cA = M::load(P, G, i, j0 - 2);
         Cell cB = M::load(P, G, i, j0 - 1);
         Cell cC = M::load(P, G, i, j0);
-        cD = M::load(P, G, i, j0 + 1);
-        rE = M::raw(P, G, i, j0 + 2);
+        W.cD = M::load(P, G, i, j0 + 1);
+        W.rE = M::raw(P, G, i, j0 + 2);
         Edge yS2, yS0, xPrev;
         M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
         M::solve(cB, cC, true, P, yS0);            // y-edge j0 - 1/2
-        M::solve(cC, cD, true, P, yN);             // y-edge j0 + 1/2
+        M::solve(cC, W.cD, true, P, W.yN);         // y-edge j0 + 1/2
         Cell lB = M::lo_cell(cB);
         M::solve(lB, cB, false, P, xPrev);         // x-edge (i - 1/2, j0 - 1)
         Cell lC = M::lo_cell(cC);
-        M::solve(lC, cC, false, P, xCur);          // x-edge (i - 1/2, j0)
+        M::solve(lC, cC, false, P, W.xCur);        // x-edge (i - 1/2, j0)
         XFl ePrev;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             ePrev.am[c] = from_hi(xPrev.am[c]);
-            xCurE.am[c] = from_hi(xCur.am[c]);
+            W.xCurE.am[c] = from_hi(W.xCur.am[c]);
         }
         ePrev.t = from_hi(xPrev.type);
-        xCurE.t = from_hi(xCur.type);
+        W.xCurE.t = from_hi(W.xCur.type);
         YPrev lo2;
         keep_yprev<M>(yS2, lo2);
-        g_tilde_r<M>(yS0, lo2, yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
-                     xCur.ap, xCur.type, xCurE.am, xCurE.t, G_S);
-        if (core && j0 < j1)
+        g_tilde_r<M, false>(yS0, lo2, W.yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
+                            W.xCur.ap, W.xCur.type, W.xCurE.am, W.xCurE.t, W.G_S);
+        if (j0 < j1)
 #pragma unroll
-            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yS0.s[p]));
-        keep_yprev<M>(yS0, yS);
-        keep_qrow<M>(cC, qC);
+            for (int p = 0; p < M::NW; ++p) W.smy = fmax_(W.smy, fabs(yS0.s[p]));
+        keep_yprev<M>(yS0, W.yS);
+        keep_qrow<M>(cC, W.qC);
     }
 
-    for (int r = j0; r < jend; ++r) {
-        const bool row_ok = r < j1;
-        Cell cE = M::cell(P, rE);
-        rE = M::raw(P, G, i, r + 3);               // in flight during this row
-        Edge yNN, xNext;
-        M::solve(cD, cE, true, P, yNN);            // y-edge r + 3/2
-        Cell lD = M::lo_cell(cD);
-        M::solve(lD, cD, false, P, xNext);         // x-edge (i - 1/2, r + 1)
-        XFl xNextE;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xNextE.am[c] = from_hi(xNext.am[c]);
-        xNextE.t = from_hi(xNext.type);
-
-        // G(i, r + 1/2); the lower neighbour of y-edge r + 1/2 is y-edge r - 1/2
-        double G_N[3];
-        g_tilde_r<M>(yN, yS, yNN, P, nuy, hnux, xCur.ap, xCur.type, xCurE.am, xCurE.t,
-                     xNext.ap, xNext.type, xNextE.am, xNextE.t, G_N);
-
-        // F(i - 1/2, r): limiter from lanes -1/+1, transverse from the y-edges
-        // of columns i-1 (lane - 1) and i (own).
-        double F_W[3] = {0.0, 0.0, 0.0};
-        {
-            double Fn[3] = {0.0, 0.0, 0.0};
-            if (P.order == 2) correction_lanes<M>(xCur, nux, Fn);
-            double yS_ap_W[3], yN_am_W[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                yS_ap_W[c] = from_lo(yS.ap[c]);
-                yN_am_W[c] = from_lo(yN.am[c]);
-            }
-            int yS_t_W = from_lo(yS.type), yN_t_W = from_lo(yN.type);
-            if (xCur.type == E_WET) {
-                to_phys(false, Fn, F_W);
-                if (P.transverse)
-                    transverse_gather<M>(xCur, false, hnuy, yS_ap_W, yS_t_W == E_WET, yN_am_W,
-                                         yN_t_W == E_WET, yS.ap, yS.type == E_WET, yN.am,
-                                         yN.type == E_WET, F_W);
-            }
+    int r = j0;
+    if (__all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
+        for (; r < jend; ++r) {
+            new_edges<M>(P, G, i, r, W);
+            if (!__all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext))) break;
+            finish_row<M, true, true>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
         }
-        double F_E[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) F_E[c] = from_hi(F_W[c]);
-
-        if (core && row_ok) {
-            double o[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                double qv = qC.q[c];
-                if (qC.upd) {
-                    qv = qv - nux * (xCur.ap[c] + xCurE.am[c]);
-                    qv = qv - nuy * (yS.ap[c] + yN.am[c]);
-                    qv = qv - nux * (F_E[c] - F_W[c]);
-                    qv = qv - nuy * (G_N[c] - G_S[c]);
-                }
-                o[c] = qv;
-            }
-            if (M::DRYFIX) {
-                // nonlinear dry-cell fix
-                if (!(o[0] > P.dry_tol)) { o[1] = 0.0; o[2] = 0.0; }
-                if (o[0] < 0.0) { o[0] = 0.0; ++nclamp; }
-            }
-            if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) ++nbad;
-            size_t k = (size_t)(G.base + (long long)r * G.pitch + i);
-            P.out0[k] = o[0];
-            P.out1[k] = o[1];
-            P.out2[k] = o[2];
+        if (r < jend) {            // the row whose new edges ended the loop
+            finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
+            ++r;
         }
-        if (xedge_in && row_ok)
-#pragma unroll
-            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nux * fabs(xCur.s[p]));
-        if (core && row_ok)
-#pragma unroll
-            for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nuy * fabs(yN.s[p]));
-
-        // move the window down one row, keeping only what is still needed
-        keep_yprev<M>(yN, yS);
-        yN = yNN;
-        xCur = xNext;
-        xCurE = xNextE;
-        keep_qrow<M>(cD, qC);
-        cD = cE;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) G_S[c] = G_N[c];
     }
+    for (; r < jend; ++r) {
+        new_edges<M>(P, G, i, r, W);
+        finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
+    }
+    const double cx = xedge_in ? nux * W.smx : 0.0, cy = core ? nuy * W.smy : 0.0;
+    cfl = fmax_(cfl, fmax_(cx, cy));
 }
 
 // Wavefront epilogue: Courant number and counters of the launch.

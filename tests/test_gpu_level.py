@@ -62,7 +62,13 @@ def setup(oracle):
         e = 30.0 * I.source_surface(X, Y, bp) + 0.2 * np.sin(X / 3e3) * np.cos(Y / 4e3)
         B.append(b)
         og = O.Grid(g.nx, g.ny, g.dx, g.dy)
-        q.append(O.init_state(og, O.Params(), O.NONLINEAR, b, e))
+        qk = O.init_state(og, O.Params(), O.NONLINEAR, b, e)
+        if k in (2, 5):
+            # a supercritical jet through the middle rows of two patches
+            r0, r1 = g.ny // 3, max(g.ny // 3 + 1, 2 * g.ny // 3)
+            h = qk[0][r0:r1]
+            qk[1][r0:r1] = np.where(h > 1e-3, 2.5 * h * np.sqrt(9.81 * h), 0.0)
+        q.append(qk)
     dts = [O.dt0(O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k]), O.Params(), O.NONLINEAR, B[k], *q[k])
            for k in range(len(ps.nx))]
     return ps, B, q, min(d for d in dts if d > 0)

@@ -145,6 +145,45 @@ def test_nl_extrap_pitch_and_small_grids(oracle, S):
         assert np.allclose(cg, cc, rtol=REL, atol=0)
 
 
+@pytest.mark.parametrize("mode", ["everywhere", "local_jet"])
+def test_nl_step_parity_supercritical(oracle, S, mode):
+    """Flow faster than the gravity-wave speed (the speeds of an edge all of
+    one sign, so that every fluctuation, limiter and transverse split takes
+    its general form), around an island of dry cells: supercritical
+    everywhere, and in a jet only, so that wavefronts meet it part-way down
+    their rows."""
+    O = oracle
+    rng = np.random.default_rng(31 if mode == "everywhere" else 32)
+    nx, ny = 190, 170
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    B = -(7.0 + 4.0 * np.sin(ii / 13.0) * np.cos(jj / 17.0)) - rng.uniform(0.0, 0.05, (ny, nx))
+    B[40:55, 100:120] = 2.0
+    h = np.maximum(0.0, -B + 0.3 * np.sin(ii / 9.0 + jj / 11.0))
+    c = np.sqrt(9.81 * h)
+    if mode == "everywhere":
+        u = (1.5 + 0.5 * np.sin(ii / 8.0)) * c
+        v = -(1.3 + 0.4 * np.cos(jj / 9.0)) * c
+    else:
+        u = 0.1 * rng.standard_normal((ny, nx))
+        v = 0.1 * rng.standard_normal((ny, nx))
+        jet = (ii - 60) ** 2 + (jj - 127) ** 2 < 15 ** 2
+        u[jet] = 2.5 * c[jet]
+        v[jet] = -1.5 * c[jet]
+    wet = h > 1e-3
+    hu, hv = np.where(wet, h * u, 0.0), np.where(wet, h * v, 0.0)
+    go, gs = pair_grids(O, S, nx, ny, 100.0, 100.0)
+    smax = max((np.abs(u) + c)[wet].max(), (np.abs(v) + c)[wet].max())
+    dt = 0.4 * 100.0 / smax
+    dts = [dt, 0.9 * dt, 0.8 * dt, 0.9 * dt]
+    q = [h, hu, hv]
+    qg, cg, _ = nl_steps_gpu(S, gs, S.Params(), B, q, dts)
+    qc, cc = nl_steps_cpu(O, go, O.Params(), B, q, dts)
+    ok, exact = compare_nl(B, qg, qc)
+    print(f"supercritical {mode}: bit-exact={exact}")
+    assert ok
+    assert np.allclose(cg, cc, rtol=REL, atol=0)
+
+
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("n,ny,seed", [(150, 110, 3), (64, 61, 7)])
 def test_adj_step_parity_2d(oracle, S, n, ny, seed):
