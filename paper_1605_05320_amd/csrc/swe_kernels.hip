@@ -145,15 +145,22 @@ struct Window {
 };
 
 // Row r, first part: row r + 2's cell data and the waves of the row's two
-// new edges (y-edge r + 3/2, x-edge (i - 1/2, r + 1)).
-template <class M>
-__device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int i, int r, Window<M> &W)
+// new edges (y-edge r + 3/2, x-edge (i - 1/2, r + 1)), without the wall and
+// dry-edge cases when all their cells are wet on every lane (lane 0's x-edge,
+// whose west cell is a zero fill, reaches no result and is not asked).
+template <class M, bool WETPATH>
+__device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int lane, int i, int r, Window<M> &W)
 {
     W.cE = M::cell(P, W.rE);
     W.rE = M::raw(P, G, i, r + 3);                 // in flight during this row
-    M::waves(W.cD, W.cE, true, P, W.yNN);
     typename M::Cell lD = M::lo_cell(W.cD);
-    M::waves(lD, W.cD, false, P, W.xNext);
+    if (WETPATH && __all(W.cD.wet && W.cE.wet && (lD.wet || lane == 0))) {
+        M::template waves<true>(W.cD, W.cE, true, P, W.yNN);
+        M::template waves<true>(lD, W.cD, false, P, W.xNext);
+    } else {
+        M::template waves<false>(W.cD, W.cE, true, P, W.yNN);
+        M::template waves<false>(lD, W.cD, false, P, W.xNext);
+    }
 }
 
 // Row r, second part: fluctuations of the new edges, correction fluxes,
@@ -231,12 +238,11 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
 // (same values); from the first row where that fails the rest of the march
 // runs the general forms.  The Courant number is nu max|s|, which equals the
 // largest nu|s| exactly (rounding is monotonic).
-template <class M>
+template <class M, bool WETPATH = true, bool SUBPATH = true>
 __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
                                       int jend, bool core, bool xedge_in, double dx, double dy,
                                       double &cfl, int &nclamp, int &nbad)
 {
-    (void)lane;
     const double nux = P.dt / dx, nuy = P.dt / dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
     using Cell = typename M::Cell;
@@ -277,9 +283,9 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     }
 
     int r = j0;
-    if (__all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
+    if (SUBPATH && __all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
         for (; r < jend; ++r) {
-            new_edges<M>(P, G, i, r, W);
+            new_edges<M, WETPATH>(P, G, lane, i, r, W);
             if (!__all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext))) break;
             finish_row<M, true, true>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
         }
@@ -289,7 +295,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         }
     }
     for (; r < jend; ++r) {
-        new_edges<M>(P, G, i, r, W);
+        new_edges<M, WETPATH>(P, G, lane, i, r, W);
         finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
     }
     const double cx = xedge_in ? nux * W.smx : 0.0, cy = core ? nuy * W.smy : 0.0;
@@ -351,7 +357,7 @@ __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L,
     G.base = pt.offset;
     const int rows = L.pass_rows[pass];
     const int row0 = L.pass_row0 ? L.pass_row0[pass] : 0;
-    march<M>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
+    march<M, false, false>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
              pt.dx, pt.dy, cfl, nclamp, nbad);
 }
 
