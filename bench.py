@@ -301,7 +301,8 @@ def secondary(S, torch, I, np, f64):
                                                       acc, macc), 100)
     out["flag_interp_512_from_256_w34_us"] = t * 1e6
     out["flag_interp_512_from_256_w34_cells_per_s"] = n * n / t
-    # the 4096^2 grid (~0.9 GB working set, beyond the 256 MB last-level cache)
+    # the 4096^2 grid (~0.9 GB working set, beyond the 256 MB last-level cache),
+    # from the initial state (the sea mostly at rest)
     n = 4096
     b = I.basin(n, 2)
     g = S.Grid(n, n, b.grid.dx, b.grid.dy)
@@ -319,6 +320,25 @@ def secondary(S, torch, I, np, f64):
     out["step_4096_algorithmic_GBs"] = BYTES_PER_CELL_STEP * n * n / t / 1e9
     del qa, qb, B, e
     torch.cuda.empty_cache()
+    # the step with waves on every edge (noise on the surface of every wet
+    # cell), so that no row of sea at rest is skipped
+    for n, reps in ((1024, 100), (4096, 20)):
+        b = I.basin(n, 2)
+        g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+        B = torch.tensor(b.B, **f64)
+        noise = np.random.default_rng(7).uniform(-0.01, 0.01, b.B.shape)
+        e = torch.tensor(b.eta0 + noise, **f64)
+        qa = [torch.empty(n, n, **f64) for _ in range(3)]
+        qb = [torch.empty(n, n, **f64) for _ in range(3)]
+        S.swe_init(g, p, B, e, qa)
+        spd = torch.zeros(1, dtype=torch.int64, device=B.device)
+        S.swe_max_speed(g, p, B, qa, 0, spd)
+        dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
+        t = _time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), reps)
+        out[f"step_busy_{n}_cell_updates_per_s"] = n * n / t
+        out[f"step_busy_{n}_us"] = t * 1e6
+        del qa, qb, B, e
+        torch.cuda.empty_cache()
     out.update(run_bench(S, torch, I, np, f64))
     out.update(level_bench(S, torch, I, np, f64))
     return out

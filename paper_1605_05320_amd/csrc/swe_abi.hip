@@ -54,7 +54,8 @@ int wave_slots()
 
 // Rows marched per wavefront.  The smallest height of at least 8 rows (the
 // warm-up costs 2.5 rows) whose launch fits in one wave of resident
-// wavefronts; 32 when the grid is too large for that (measured flat beyond).
+// wavefronts; 24 when the grid is too large for that (measured best of 16 to
+// 64 rows on a 4096^2 grid).
 // SWE_MARCH_ROWS overrides it (tuning sweeps).
 int default_ly(int nx, int ny)
 {
@@ -65,9 +66,9 @@ int default_ly(int nx, int ny)
     }();
     if (forced > 0) return forced;
     long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
-    for (int ly = 8; ly <= 32; ++ly)
+    for (int ly = 8; ly <= 24; ++ly)
         if (strips * ((ny + ly - 1) / ly) <= wave_slots()) return ly;
-    return 32;
+    return 24;
 }
 
 // XCD-aware tile placement pays when all wavefronts of the launch are

@@ -142,6 +142,8 @@ struct Window {
     double G_S[3];           // G of edge r - 1/2
     RawCell rE;              // stored values of row r + 3, loaded one row ahead
     double smx, smy;         // largest |s| of the counted x- and y-edges
+    // the edge carries no waves on any lane of the wavefront (sea at rest)
+    bool zyS, zyN, zxCur, zyNN, zxNext;
 };
 
 // Row r, first part: row r + 2's cell data and the waves of the row's two
@@ -161,6 +163,8 @@ __device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int la
         M::template waves<false>(W.cD, W.cE, true, P, W.yNN);
         M::template waves<false>(lD, W.cD, false, P, W.xNext);
     }
+    W.zyNN = __all(M::zero_waves(W.yNN));
+    W.zxNext = __all(M::zero_waves(W.xNext));
 }
 
 // Row r, second part: fluctuations of the new edges, correction fluxes,
@@ -178,8 +182,16 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
     for (int c = 0; c < 3; ++c) xNextE.am[c] = from_hi(W.xNext.am[c]);
     xNextE.t = from_hi(W.xNext.type);
 
+    // Where the edges around row r carry no waves on any lane, both
+    // correction fluxes are zero (no limited waves, nothing to split).
     double G_N[3], F_W[3];
-    row_fluxes<M, SUB>(P, W.yN, W.yS, W.yNN, W.xCur, W.xCurE, W.xNext, xNextE, nux, nuy, hnux, hnuy, G_N, F_W);
+    if (W.zyS && W.zyN && W.zxCur && W.zxNext) {
+        G_N[0] = 0.0; G_N[1] = 0.0; G_N[2] = 0.0;
+        F_W[0] = 0.0; F_W[1] = 0.0; F_W[2] = 0.0;
+    } else {
+        row_fluxes<M, SUB>(P, W.yN, W.yS, W.yNN, W.xCur, W.xCurE, W.xNext, xNextE, nux, nuy, hnux, hnuy, G_N,
+                           F_W);
+    }
     double F_E[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) F_E[c] = from_hi(F_W[c]);
@@ -223,6 +235,9 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
     W.xCurE = xNextE;
     keep_qrow<M>(W.cD, W.qC);
     W.cD = W.cE;
+    W.zyS = W.zyN;
+    W.zyN = W.zyNN;
+    W.zxCur = W.zxNext;
 #pragma unroll
     for (int c = 0; c < 3; ++c) W.G_S[c] = G_N[c];
 }
@@ -280,6 +295,9 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
             for (int p = 0; p < M::NW; ++p) W.smy = fmax_(W.smy, fabs(yS0.s[p]));
         keep_yprev<M>(yS0, W.yS);
         keep_qrow<M>(cC, W.qC);
+        W.zyS = __all(M::zero_waves(yS0));
+        W.zyN = __all(M::zero_waves(W.yN));
+        W.zxCur = __all(M::zero_waves(W.xCur));
     }
 
     int r = j0;
