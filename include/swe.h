@@ -187,8 +187,9 @@ SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const d
 /*
  * Device-side time-step control (the CFL rule of swe_run, phase B), so that a
  * sequence of forward steps needs no host round-trip and can be captured in
- * a HIP graph.  The control block lives in device memory; the state
- * alternates between two plane sets a (cur = 0) and b (cur = 1).
+ * a HIP graph.  The control block lives in device memory (256-byte aligned
+ * for speed: its Courant-number words then sit on lines of their own); the
+ * state alternates between two plane sets a (cur = 0) and b (cur = 1).
  * After each attempt of length dt with Courant number cfl:
  *   cfl > cfl_max: rejected, dt = dt*cfl_desired/cfl;
  *   else accepted: cur ^= 1, t = (final ? t_out : t + dt),
@@ -199,6 +200,8 @@ SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const d
  * attempt costs exactly one kernel launch; swe_advance ends with one small
  * kernel that resolves the last attempt into ctl->s.
  */
+#define SWE_CTL_SPREAD 32
+
 typedef struct {
     double t;               /* time of the current state */
     double dt;              /* length of the next attempt */
@@ -217,7 +220,13 @@ typedef struct {
     int32_t n_flag_calls;   /* flag passes run by swe_advance_flagged */
     int32_t reserved;
     swe_ctl_state slot[2];  /* kernel-internal: state of the running attempts */
-    uint64_t ring[3];       /* kernel-internal: Courant numbers of the running attempts */
+    uint8_t pad_[88];       /* kernel-internal: puts the ring 256 bytes in */
+    /* kernel-internal: Courant numbers of the running attempts, attempt k's
+     * being the largest of ring[k][j][0] over j < SWE_CTL_SPREAD: the
+     * wavefronts of a launch spread their atomic maxima over these words, one
+     * 128-byte line each (atomics on one word are serialised, which made a
+     * single word cost microseconds per launch) */
+    uint64_t ring[3][SWE_CTL_SPREAD][16];
 } swe_ctl;
 
 /* swe_ctl_set - (device) ctl := {t, dt clamped to t_out - t, t_out, cur,

@@ -158,6 +158,8 @@ swe::KParams make_kparams(const swe_grid *g, const swe_params *p, const double *
     k.out0 = out.f0; k.out1 = out.f1; k.out2 = out.f2;
     if (sc) {
         k.cfl_bits = (unsigned long long *)&sc->cfl_bits;
+        k.cfl_spread = 1;
+        k.cfl_stride = 1;
         k.n_clamped = &sc->n_clamped;
         k.n_nonfinite = &sc->n_nonfinite;
     }

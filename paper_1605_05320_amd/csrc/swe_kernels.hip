@@ -328,7 +328,9 @@ __device__ __forceinline__ void march_epilogue(const KParams &P, int lane, doubl
     if (lane == 0) {
         if (mc && P.n_clamped) atomicAdd(P.n_clamped, __popcll(mc));
         if (mb && P.n_nonfinite) atomicAdd(P.n_nonfinite, __popcll(mb));
-        if (P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+        if (P.cfl_bits)
+            atomicMax(P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0),
+                      (unsigned long long)__double_as_longlong(cfl));
     }
 }
 
@@ -432,8 +434,9 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
     unsigned long long last_bits = 0;
     bool ran = false;
     for (int a = 0; a < n_steps && !S.done; ++a) {
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            __hip_atomic_store(&c->ring[(a + 1) % 3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (blockIdx.x == 0 && threadIdx.x < SWE_CTL_SPREAD)
+            __hip_atomic_store(&c->ring[(a + 1) % 3][threadIdx.x][0], 0ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         KParams Q = P;
         Q.dt = S.dt;
         if (S.cur) {
@@ -441,21 +444,26 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
             Q.out0 = const_cast<double *>(P.in0); Q.out1 = const_cast<double *>(P.in1);
             Q.out2 = const_cast<double *>(P.in2);
         }
-        Q.cfl_bits = (unsigned long long *)&c->ring[a % 3];
+        aim_ring(Q, c, a % 3);
         double cfl = 0.0;
         int nclamp = 0, nbad = 0;
         for (int j = blockIdx.x; j < L.n_jobs; j += nw)
             for (int ps = L.job_pass[j]; ps < L.job_pass[j + 1]; ++ps) level_pass<NL>(Q, L, ps, cfl, nclamp, nbad);
         march_epilogue(Q, threadIdx.x, cfl, nclamp, nbad);
         if (!level_barrier(L.sync, nw)) break;
-        last_bits = __hip_atomic_load(&c->ring[a % 3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last_bits = 0;
+        for (int j = 0; j < SWE_CTL_SPREAD; ++j) {
+            const unsigned long long v =
+                __hip_atomic_load(&c->ring[a % 3][j][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last_bits = v > last_bits ? v : last_bits;
+        }
         S = ctl_apply(S, __longlong_as_double((long long)last_bits), P.cfl_desired, P.cfl_max);
         ran = true;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->s = S;
         if (ran) c->cfl_bits = last_bits;
-        c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
+        clear_ring(c);
     }
 }
 
@@ -502,12 +510,15 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
 #pragma unroll
         for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nu * fabs(x.s[p]));
     cfl = wave_max(cfl);
-    if (lane == 0 && P.cfl_bits) atomicMax(P.cfl_bits, (unsigned long long)__double_as_longlong(cfl));
+    if (lane == 0 && P.cfl_bits)
+        atomicMax(P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0),
+                  (unsigned long long)__double_as_longlong(cfl));
 }
 
 // ---------------------------------------------------------------------------
 // Device-side step control (single thread).
 // ---------------------------------------------------------------------------
+
 __global__ void k_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -527,7 +538,7 @@ __global__ void k_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur
     c->n_clamped = 0;
     c->n_nonfinite = 0;
     c->n_flag_calls = 0;
-    c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
+    clear_ring(c);
 }
 
 __global__ void k_ctl_retarget(swe_ctl *c, double t_out)
@@ -545,10 +556,10 @@ __global__ void k_ctl_retarget(swe_ctl *c, double t_out)
 __global__ void k_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_max)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0 || n < 1) return;
-    unsigned long long bits = c->ring[(n - 1) % 3];
+    unsigned long long bits = ring_bits(c, (n - 1) % 3);
     c->s = ctl_apply(c->slot[(n - 1) & 1], __longlong_as_double((long long)bits), cfl_desired, cfl_max);
     c->cfl_bits = bits;
-    c->ring[0] = 0; c->ring[1] = 0; c->ring[2] = 0;
+    clear_ring(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,7 +699,8 @@ __global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
 {
     swe_ctl *c = C.ctl;
     swe_ctl_state S = ctl_apply(c->slot[C.attempt & 1],
-                                __longlong_as_double((long long)c->ring[C.attempt % 3]), C.cfl_desired, C.cfl_max);
+                                __longlong_as_double((long long)ring_bits(c, C.attempt % 3)), C.cfl_desired,
+                                C.cfl_max);
     if (!S.last_accepted) return;
     if (!(S.done || S.n_accepted % C.flag_every == 0)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) c->n_flag_calls = c->n_flag_calls + 1;

@@ -61,6 +61,9 @@ class swe_result(C.Structure):
                 ("dt_adj", C.c_double), ("t_end", C.c_double)]
 
 
+CTL_SPREAD = 32     # SWE_CTL_SPREAD
+
+
 class swe_ctl_state(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("t_out", C.c_double),
                 ("cur", C.c_int32), ("final_step", C.c_int32), ("done", C.c_int32),
@@ -70,7 +73,8 @@ class swe_ctl_state(C.Structure):
 class swe_ctl(C.Structure):
     _fields_ = [("s", swe_ctl_state), ("cfl_bits", C.c_uint64), ("n_clamped", C.c_int32),
                 ("n_nonfinite", C.c_int32), ("n_flag_calls", C.c_int32), ("reserved", C.c_int32),
-                ("slot", swe_ctl_state * 2), ("ring", C.c_uint64 * 3)]
+                ("slot", swe_ctl_state * 2), ("pad_", C.c_uint8 * 88),
+                ("ring", ((C.c_uint64 * 16) * CTL_SPREAD) * 3)]
 
     # flat access to the resolved state
     def __getattr__(self, name):
