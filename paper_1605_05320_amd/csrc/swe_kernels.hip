@@ -271,13 +271,37 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         W.cD = M::load(P, G, i, j0 + 1);
         W.rE = M::raw(P, G, i, j0 + 2);
         Edge yS2, yS0, xPrev;
-        M::solve(cA, cB, true, P, yS2);            // y-edge j0 - 3/2
-        M::solve(cB, cC, true, P, yS0);            // y-edge j0 - 1/2
-        M::solve(cC, W.cD, true, P, W.yN);         // y-edge j0 + 1/2
         Cell lB = M::lo_cell(cB);
-        M::solve(lB, cB, false, P, xPrev);         // x-edge (i - 1/2, j0 - 1)
         Cell lC = M::lo_cell(cC);
-        M::solve(lC, cC, false, P, W.xCur);        // x-edge (i - 1/2, j0)
+        // y-edges j0 - 3/2, j0 - 1/2, j0 + 1/2; x-edges (i - 1/2, j0 - 1), (i - 1/2, j0)
+        if (WETPATH && __all(cA.wet && cB.wet && cC.wet && W.cD.wet && ((lB.wet && lC.wet) || lane == 0))) {
+            M::template waves<true>(cA, cB, true, P, yS2);
+            M::template waves<true>(cB, cC, true, P, yS0);
+            M::template waves<true>(cC, W.cD, true, P, W.yN);
+            M::template waves<true>(lB, cB, false, P, xPrev);
+            M::template waves<true>(lC, cC, false, P, W.xCur);
+        } else {
+            M::template waves<false>(cA, cB, true, P, yS2);
+            M::template waves<false>(cB, cC, true, P, yS0);
+            M::template waves<false>(cC, W.cD, true, P, W.yN);
+            M::template waves<false>(lB, cB, false, P, xPrev);
+            M::template waves<false>(lC, cC, false, P, W.xCur);
+        }
+        const bool sub5 = SUBPATH && __all(sub_edge<M>(yS2) && sub_edge<M>(yS0) && sub_edge<M>(W.yN) &&
+                                           sub_edge<M>(xPrev) && sub_edge<M>(W.xCur));
+        if (sub5) {
+            M::template fluct<true>(yS2, true);
+            M::template fluct<true>(yS0, true);
+            M::template fluct<true>(W.yN, true);
+            M::template fluct<true>(xPrev, false);
+            M::template fluct<true>(W.xCur, false);
+        } else {
+            M::template fluct<false>(yS2, true);
+            M::template fluct<false>(yS0, true);
+            M::template fluct<false>(W.yN, true);
+            M::template fluct<false>(xPrev, false);
+            M::template fluct<false>(W.xCur, false);
+        }
         XFl ePrev;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -286,18 +310,25 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         }
         ePrev.t = from_hi(xPrev.type);
         W.xCurE.t = from_hi(W.xCur.type);
+        W.zyS = __all(M::zero_waves(yS0));
+        W.zyN = __all(M::zero_waves(W.yN));
+        W.zxCur = __all(M::zero_waves(W.xCur));
         YPrev lo2;
         keep_yprev<M>(yS2, lo2);
-        g_tilde_r<M, false>(yS0, lo2, W.yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
-                            W.xCur.ap, W.xCur.type, W.xCurE.am, W.xCurE.t, W.G_S);
+        if (W.zyS && W.zxCur && __all(M::zero_waves(xPrev))) {
+            W.G_S[0] = 0.0; W.G_S[1] = 0.0; W.G_S[2] = 0.0;
+        } else if (sub5) {
+            g_tilde_r<M, true>(yS0, lo2, W.yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
+                               W.xCur.ap, W.xCur.type, W.xCurE.am, W.xCurE.t, W.G_S);
+        } else {
+            g_tilde_r<M, false>(yS0, lo2, W.yN, P, nuy, hnux, xPrev.ap, xPrev.type, ePrev.am, ePrev.t,
+                                W.xCur.ap, W.xCur.type, W.xCurE.am, W.xCurE.t, W.G_S);
+        }
         if (j0 < j1)
 #pragma unroll
             for (int p = 0; p < M::NW; ++p) W.smy = fmax_(W.smy, fabs(yS0.s[p]));
         keep_yprev<M>(yS0, W.yS);
         keep_qrow<M>(cC, W.qC);
-        W.zyS = __all(M::zero_waves(yS0));
-        W.zyN = __all(M::zero_waves(W.yN));
-        W.zxCur = __all(M::zero_waves(W.xCur));
     }
 
     int r = j0;
