@@ -427,9 +427,11 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
     host clustering, injection of the coarse state into the 2x refined
     patches, and steps of the refined level."""
     fl = flags.cpu().numpy()
-    t = time.perf_counter()
-    boxes = S.cluster(fl, 0.7, 4, 32)
-    t_cluster = time.perf_counter() - t
+    t_cluster = float("inf")
+    for _ in range(5):              # host call: best of five
+        t = time.perf_counter()
+        boxes = S.cluster(fl, 0.7, 4, 32)
+        t_cluster = min(t_cluster, time.perf_counter() - t)
     if not boxes:
         return {"boxes": 0}
     nxp = [nx * ratio for (_, _, nx, _) in boxes]
