@@ -334,7 +334,7 @@ def secondary(S, torch, I, np, f64):
         spd = torch.zeros(1, dtype=torch.int64, device=B.device)
         S.swe_max_speed(g, p, B, qa, 0, spd)
         dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
-        t = _time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), reps)
+        t = min(_time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), reps) for _ in range(3))
         out[f"step_busy_{n}_cell_updates_per_s"] = n * n / t
         out[f"step_busy_{n}_us"] = t * 1e6
         del qa, qb, B, e
