@@ -52,10 +52,13 @@ int wave_slots()
     return slots;
 }
 
-// Rows marched per wavefront.  The smallest height of at least 8 rows (the
-// warm-up costs 2.5 rows) whose launch fits in one wave of resident
-// wavefronts; 24 when the grid is too large for that (measured best of 16 to
-// 64 rows on a 4096^2 grid).
+// Rows marched per wavefront.  The smallest height of at least 2 rows whose
+// launch fits in one wave of resident wavefronts (a march's time is its rows
+// plus a warm-up of about 2.5 rows, so while the launch fits, shorter marches
+// finish sooner: measured 11.5 us at 2 rows against 24.6 us at 8 rows on a
+// 256^2 grid, 20.0 us at 3 rows against 25.7 us at 8 on 512^2); 24 when the
+// grid is too large for that (measured best of 16 to 64 rows on a 4096^2
+// grid).
 // SWE_MARCH_ROWS overrides it (tuning sweeps).
 int default_ly(int nx, int ny)
 {
@@ -66,7 +69,7 @@ int default_ly(int nx, int ny)
     }();
     if (forced > 0) return forced;
     long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
-    for (int ly = 8; ly <= 24; ++ly)
+    for (int ly = 2; ly <= 24; ++ly)
         if (strips * ((ny + ly - 1) / ly) <= wave_slots()) return ly;
     return 24;
 }
