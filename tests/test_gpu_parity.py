@@ -541,6 +541,27 @@ def test_full_size_1024_sampled_steps(oracle, S):
     assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
 
 
+@pytest.mark.parametrize("nx,ny", [(1024, 1024), (4096, 720)])
+def test_large_grids_waves_on_every_edge(oracle, S, nx, ny):
+    """Surface noise on every wet cell, so that no row is at rest and the
+    step runs its subcritical all-wet forms on most wavefronts: the 1024^2
+    benchmark grid (10-row marches, all resident) and a 4096-wide grid whose
+    launch exceeds the resident slots (24-row marches).  Two steps, every
+    element compared."""
+    O = oracle
+    b = I.basin(nx, 2, ny=ny)
+    go, gs = pair_grids(O, S, nx, ny, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    noise = np.random.default_rng(9).uniform(-0.01, 0.01, b.B.shape)
+    q = O.init_state(go, p, O.NONLINEAR, b.B, b.eta0 + noise)
+    dt = O.dt0(go, p, O.NONLINEAR, b.B, *q)
+    qc, cc = nl_steps_cpu(O, go, p, b.B, q, [dt, 0.9 * dt])
+    qg, cg, _ = nl_steps_gpu(S, gs, S.Params(), b.B, q, [dt, 0.9 * dt])
+    ok, exact = compare_nl(b.B, qg, qc)
+    print(f"{nx}x{ny} waves on every edge: bit-exact={exact}")
+    assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
+
+
 # --------------------------------------------------------------------------
 def _oracle_controlled(O, g, p, B, q, dt, t, t_out, n_attempts, cfl_d, cfl_max):
     """Host mirror of the device-side control rule (same rule as the driver)."""
