@@ -567,7 +567,9 @@ def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, 
     Each served result is compared bit for bit with its sequential one."""
     trace = I.arrivals(n_req, 1.0, nmin, nmax, seed=seed)
     reqs = []
-    for a in trace:
+    for k, a in enumerate(trace):
+        if k % 32 == 0:
+            print(f"serve: building request {k} of {n_req}", file=sys.stderr, flush=True)
         b = I.basin(a.n, a.seed)
         g = S.Grid(a.n, a.n, b.grid.dx, b.grid.dy)
         reqs.append(S.Request(g, S.Params(), b.B, b.eta0, b.target, 0.0, ts, tf, K, tol,
@@ -581,7 +583,10 @@ def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, 
     def run(active, realtime):
         t = time.perf_counter()
         _, st = S.serve(reqs, arena, active, realtime=realtime)
-        return time.perf_counter() - t, st
+        el = time.perf_counter() - t
+        print(f"serve: {n_req} requests, {active} in flight, {'realtime' if realtime else 'offline'}: "
+              f"{el:.1f} s", file=sys.stderr, flush=True)
+        return el, st
 
     el_seq, st_seq = run(1, False)
     ref = [(r.flag_acc.copy(), r.maxip_acc.copy(), [q.copy() for q in r.q]) for r in reqs]
