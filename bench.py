@@ -580,9 +580,14 @@ def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, 
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     S.serve(reqs[:1], arena, 1)                         # warm-up (code objects, first launches)
 
+    def progress(k, count=[0]):
+        count[0] += 1
+        if count[0] % 16 == 0:
+            print(f"serve: {count[0] % n_req or n_req} of {n_req} done", file=sys.stderr, flush=True)
+
     def run(active, realtime):
         t = time.perf_counter()
-        _, st = S.serve(reqs, arena, active, realtime=realtime)
+        _, st = S.serve(reqs, arena, active, realtime=realtime, on_done=progress, check=False)
         el = time.perf_counter() - t
         print(f"serve: {n_req} requests, {active} in flight, {'realtime' if realtime else 'offline'}: "
               f"{el:.1f} s", file=sys.stderr, flush=True)
@@ -628,6 +633,11 @@ def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, 
         "served_realtime": dict(lat(st_rt), scen_per_s=round(n_req / span(st_rt), 3)),
         "p99_speedup": round(lat(st_rt_seq)["p99_s"] / max(lat(st_rt)["p99_s"], 1e-9), 3),
         "results_identical_to_sequential": bool(ok_cap and ok_rt),
+        # requests whose run ended with an error (the same ones in every pass):
+        # index, grid side and status
+        "failed": [[k, trace[k].n, s["status"]] for k, s in enumerate(st_seq) if s["status"] != 0],
+        "failed_same_in_every_pass": all([s["status"] for s in x] == [s["status"] for s in st_seq]
+                                         for x in (st_cap, st_rt_seq, st_rt)),
     }
 
 

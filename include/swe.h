@@ -52,7 +52,8 @@ extern "C" {
 typedef enum {
     SWE_OK = 0,
     SWE_E_INVAL = -1,      /* bad argument (null pointer, size, dt, alias, ...) */
-    SWE_E_CFL = -2,        /* the driver could not find an accepted step */
+    SWE_E_CFL = -2,        /* the driver could not find an accepted step, or its time step
+                              collapsed (a million times below the initial one: a blown-up state) */
     SWE_E_HIP = -3,        /* a HIP runtime call failed */
     SWE_E_NOMEM = -4,      /* the caller's workspace is too small */
     SWE_E_NONFINITE = -5,  /* a non-finite value appeared in the state */
@@ -490,6 +491,12 @@ typedef struct {
     size_t arena_bytes;
     int32_t max_active;         /* scenarios in flight, one stream and host thread each (>= 1) */
     int32_t realtime;           /* 1: a request is not admitted before its arrival time */
+    /* optional (may be NULL): called on a worker thread after a request's
+     * results are back, with its index in req, a copy of its complete stats
+     * and user; calls come in completion order and may overlap; the callback
+     * must not call swe_serve */
+    void (*on_done)(int32_t index, const swe_request_stats *stats, void *user);
+    void *user;
 } swe_serve_config;
 
 /* Device bytes one request occupies while it runs (0 on bad input). */
@@ -559,7 +566,10 @@ SWE_API size_t swe_run_workspace_bytes(const swe_problem *pb);
  *      a multiple of flag_every } until tf.
  * Synchronises `stream` (it reads the Courant number of each step) and
  * returns when the run has completed.  workspace: device, at least
- * swe_run_workspace_bytes(pb) bytes, 256-byte aligned.
+ * swe_run_workspace_bytes(pb) bytes, 256-byte aligned.  Errors: SWE_E_NONFINITE
+ * (a non-finite state), SWE_E_CFL (more than 1000 rejected attempts, or the
+ * time step fell a million times below dt0 or stopped advancing t: the state
+ * has blown up, e.g. a thin fast layer at a shoreline wall).
  */
 SWE_API swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_bytes,
                    swe_result *res, void *stream);

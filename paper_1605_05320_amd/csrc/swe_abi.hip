@@ -644,14 +644,27 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         fl.flags_final = pb->flags_at ? pb->flags_at + (size_t)j * plane : w.flags;
-        int rounds = 0;
+        int rounds = 0, stalled = 0;
         while (!hc.s.done) {
+            const double t_before = hc.s.t;
+            if (!(hc.s.dt >= 1e-6 * dt0))
+                return fail(SWE_E_CFL, "time step collapsed at t = %g (dt = %g, initial %g)", hc.s.t, hc.s.dt,
+                            dt0);
             double need = std::ceil((tout - hc.s.t) / hc.s.dt);
             int n = (int)std::min(std::max(need, 0.0) + 2.0, 100000.0);
             if ((st = swe_advance_flagged(G, P, pb->B, A, Bf, w.ctl, n, &fl, stream)) != SWE_OK) return st;
             HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (hc.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state near t = %g", hc.s.t);
+            // A time step a million times below the initial one means the
+            // wave speeds grew a million-fold: the state has blown up (a round
+            // of such steps would not reach the output time in any useful
+            // time, and once dt is below the resolution of t no step advances
+            // it at all).
+            stalled = hc.s.t > t_before ? 0 : stalled + 1;
+            if (!hc.s.done && (!(hc.s.dt >= 1e-6 * dt0) || stalled >= 3))
+                return fail(SWE_E_CFL, "time step collapsed at t = %g (dt = %g, initial %g)", hc.s.t, hc.s.dt,
+                            dt0);
             if (++rounds > 1000 || hc.s.n_rejected > 1000) return fail(SWE_E_CFL, "no progress at t = %g", hc.s.t);
         }
         if (pb->surface_flags_at) {

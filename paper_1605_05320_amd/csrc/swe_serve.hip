@@ -222,18 +222,23 @@ swe_status swe_serve(const swe_request *req, int32_t n, const swe_serve_config *
                 // a failed run may leave work in flight on the block: drain it before the block is reused
                 if (rs != SWE_OK) (void)hipStreamSynchronize(streams[w]);
                 double fin = now_s(t0);
-                std::lock_guard<std::mutex> lk(mu);
-                stats[jb.req].status = rs;
-                stats[jb.req].n_adj_steps = st.n_adj_steps;
-                stats[jb.req].n_fwd_steps = st.n_fwd_steps;
-                stats[jb.req].finished = fin;
-                stats[jb.req].latency = fin - (cfg->realtime ? req[jb.req].arrival : 0.0);
-                if (rs != SWE_OK && first_err == SWE_OK) first_err = rs;
-                arena.release(jb.off, lay[jb.req].total);
-                job[w].req = -1;
-                ready_slots.push_back(w);
-                ++done_count;
-                cv.notify_all();
+                swe_request_stats done;
+                {
+                    std::lock_guard<std::mutex> lk(mu);
+                    stats[jb.req].status = rs;
+                    stats[jb.req].n_adj_steps = st.n_adj_steps;
+                    stats[jb.req].n_fwd_steps = st.n_fwd_steps;
+                    stats[jb.req].finished = fin;
+                    stats[jb.req].latency = fin - (cfg->realtime ? req[jb.req].arrival : 0.0);
+                    done = stats[jb.req];
+                    if (rs != SWE_OK && first_err == SWE_OK) first_err = rs;
+                    arena.release(jb.off, lay[jb.req].total);
+                    job[w].req = -1;
+                    ready_slots.push_back(w);
+                    ++done_count;
+                    cv.notify_all();
+                }
+                if (cfg->on_done) cfg->on_done(jb.req, &done, cfg->user);
             }
         });
     }

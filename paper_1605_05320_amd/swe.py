@@ -333,9 +333,12 @@ class swe_request_stats(C.Structure):
                 ("n_fwd_steps", C.c_int32), ("bytes", C.c_size_t)]
 
 
+SERVE_DONE_FN = C.CFUNCTYPE(None, C.c_int32, C.POINTER(swe_request_stats), C.c_void_p)
+
+
 class swe_serve_config(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("max_active", C.c_int32),
-                ("realtime", C.c_int32)]
+                ("realtime", C.c_int32), ("on_done", SERVE_DONE_FN), ("user", C.c_void_p)]
 
 
 class Request:
@@ -373,14 +376,16 @@ def serve_footprint(req: Request) -> int:
     return lib().swe_serve_footprint(C.byref(req.c))
 
 
-def serve(reqs, arena, max_active: int, realtime: bool = False, check: bool = True):
+def serve(reqs, arena, max_active: int, realtime: bool = False, check: bool = True, on_done=None):
     """Run swe_serve over a list of Request (ordered by arrival) with the
-    device tensor ``arena`` as memory.  Returns (status, list of stats dicts)."""
+    device tensor ``arena`` as memory; on_done(index) is called (on a worker
+    thread) as each request completes.  Returns (status, list of stats dicts)."""
     n = len(reqs)
     arr = (swe_request * n)(*[r.c for r in reqs])
     st = (swe_request_stats * n)()
+    cb = SERVE_DONE_FN(lambda k, s, u: on_done(k)) if on_done else SERVE_DONE_FN()
     cfg = swe_serve_config(arena.data_ptr(), arena.numel() * arena.element_size(), max_active,
-                           1 if realtime else 0)
+                           1 if realtime else 0, cb, None)
     rc = lib().swe_serve(arr, C.c_int32(n), C.byref(cfg), st)
     if check:
         _check(rc)

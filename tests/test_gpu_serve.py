@@ -118,3 +118,41 @@ def test_realtime_admission_waits_for_arrival(S):
         assert s["status"] == 0
         assert s["admitted"] >= r.c.arrival
         assert abs(s["latency"] - (s["finished"] - r.c.arrival)) < 1e-9
+
+
+def test_on_done_reports_every_request_once(S):
+    import threading
+    reqs = trace(S, n_req=6, nmin=48, nmax=96)
+    arena = arena_for(S, reqs, copies=3)
+    seen, lock = [], threading.Lock()
+
+    def done(k):
+        with lock:
+            seen.append(k)
+
+    _, st = S.serve(reqs, arena, 3, on_done=done)
+    assert sorted(seen) == list(range(len(reqs)))
+    # completion order: each report comes after that request finished
+    fin = [st[k]["finished"] for k in seen]
+    assert all(f > 0.0 for f in fin)
+
+
+def test_blown_up_scenario_fails_fast_and_the_rest_complete(S):
+    """Basin seed 1114 on a 1414^2 grid: after ~1800 steps the wall treatment
+    at the shoreline leaves a millimetre-thin layer moving at hundreds of m/s
+    and the time step collapses (the oracle does the same, byte for byte).
+    The run must end with SWE_E_CFL within seconds, and a request served
+    beside it must complete normally."""
+    import time
+    b = I.basin(1414, 1114)
+    g = S.Grid(1414, 1414, b.grid.dx, b.grid.dy)
+    bad = S.Request(g, S.Params(), b.B, b.eta0, b.target, 0.0, 3600.0, 7200.0, 32, 1e-4, flag_every=4)
+    good, _ = make_request(S, 96, 1003)
+    arena = arena_for(S, [bad, good], copies=2)
+    t = time.perf_counter()
+    rc, st = S.serve([bad, good], arena, 2, check=False)
+    el = time.perf_counter() - t
+    print(f"blown-up scenario: status {st[0]['status']} after {el:.1f} s; beside it: {st[1]['status']}")
+    assert st[0]["status"] == S.E_CFL and rc == S.E_CFL
+    assert st[1]["status"] == 0 and st[1]["n_fwd_steps"] > 0
+    assert el < 60.0
