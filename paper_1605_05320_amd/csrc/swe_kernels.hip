@@ -10,7 +10,7 @@
 // correction flux G of edge r-1/2), and everything it needs from the
 // columns left and right comes from neighbouring lanes by cross-lane
 // shuffles.  So each edge of a strip is solved exactly once, the state is
-// read once per strip (plus 4 halo rows per chunk and 4 halo columns per
+// read once per strip (plus 5 halo rows per march and 4 halo columns per
 // strip) and written once, there is no LDS footprint and no barrier.
 #include "swe_device.h"
 #include "swe_internal.h"
