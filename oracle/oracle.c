@@ -596,7 +596,23 @@ int or_swe_step(const or_grid *G, const or_params *P, const double *B,
             ncl++;
         }
     }
-    if (cfl_out) *cfl_out = cfl2d(&E, nux, nuy);
+    /* Courant number: the edges' wave speeds, and each wet interior cell's
+     * own speeds |u| + sqrt(g) sqrt(h), |v| + sqrt(g) sqrt(h).  The cell
+     * speeds matter where a thin layer moves fast next to a wall or a much
+     * deeper neighbour: the Roe averages of its edges hide its velocity. */
+    if (cfl_out) {
+        double cfl = cfl2d(&E, nux, nuy);
+        const double sg = sqrt(P->g);
+        for (int j = 0; j < ny; j++)
+            for (int i = 0; i < nx; i++) {
+                size_t k = (size_t)(j + 2) * Q[0].px + (i + 2);
+                if (!wp[k]) continue;
+                const double c = sg * sq[k];
+                cfl = MAXD(cfl, nux * (fabs(uu[k]) + c));
+                cfl = MAXD(cfl, nuy * (fabs(vv[k]) + c));
+            }
+        *cfl_out = cfl;
+    }
     if (n_clamped) *n_clamped = ncl;
 
     edges_free(&E);

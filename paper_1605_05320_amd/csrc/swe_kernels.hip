@@ -142,6 +142,7 @@ struct Window {
     double G_S[3];           // G of edge r - 1/2
     RawCell rE;              // stored values of row r + 3, loaded one row ahead
     double smx, smy;         // largest |s| of the counted x- and y-edges
+    double scell;            // largest cell term of the Courant number (rows j0 .. j1-1)
     // the edge carries no waves on any lane of the wavefront (sea at rest)
     bool zyS, zyN, zxCur, zyNN, zxNext;
 };
@@ -151,10 +152,12 @@ struct Window {
 // dry-edge cases when all their cells are wet on every lane (lane 0's x-edge,
 // whose west cell is a zero fill, reaches no result and is not asked).
 template <class M, bool WETPATH>
-__device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int lane, int i, int r, Window<M> &W)
+__device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int lane, int i, int r, int j1, double sg,
+                                          double nux, double nuy, Window<M> &W)
 {
     W.cE = M::cell(P, W.rE);
     W.rE = M::raw(P, G, i, r + 3);                 // in flight during this row
+    if (r + 2 < j1) W.scell = fmax_(W.scell, M::cell_cfl(W.cE, sg, nux, nuy));
     typename M::Cell lD = M::lo_cell(W.cD);
     if (WETPATH && __all(W.cD.wet && W.cE.wet && (lD.wet || lane == 0))) {
         M::template waves<true>(W.cD, W.cE, true, P, W.yNN);
@@ -251,8 +254,9 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
 // While every lane's edges have s_1 < 0 < s_NW (or are dry) - the case
 // everywhere in subcritical flow - rows run the forms that know those signs
 // (same values); from the first row where that fails the rest of the march
-// runs the general forms.  The Courant number is nu max|s|, which equals the
-// largest nu|s| exactly (rounding is monotonic).
+// runs the general forms.  The Courant number is nu max|s| over the edges,
+// which equals the largest nu|s| exactly (rounding is monotonic), and the
+// cells' own terms (nonlinear model) over the march's rows.
 template <class M, bool WETPATH = true, bool SUBPATH = true>
 __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
                                       int jend, bool core, bool xedge_in, double dx, double dy,
@@ -261,15 +265,19 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     const double nux = P.dt / dx, nuy = P.dt / dy;
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
     using Cell = typename M::Cell;
+    const double sg = sqrt(P.g);
     Window<M> W;
     W.smx = 0.0;
     W.smy = 0.0;
+    W.scell = 0.0;
     {
         Cell cA = M::load(P, G, i, j0 - 2);
         Cell cB = M::load(P, G, i, j0 - 1);
         Cell cC = M::load(P, G, i, j0);
         W.cD = M::load(P, G, i, j0 + 1);
         W.rE = M::raw(P, G, i, j0 + 2);
+        if (j0 < j1) W.scell = fmax_(W.scell, M::cell_cfl(cC, sg, nux, nuy));
+        if (j0 + 1 < j1) W.scell = fmax_(W.scell, M::cell_cfl(W.cD, sg, nux, nuy));
         Edge yS2, yS0, xPrev;
         Cell lB = M::lo_cell(cB);
         Cell lC = M::lo_cell(cC);
@@ -334,7 +342,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     int r = j0;
     if (SUBPATH && __all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
         for (; r < jend; ++r) {
-            new_edges<M, WETPATH>(P, G, lane, i, r, W);
+            new_edges<M, WETPATH>(P, G, lane, i, r, j1, sg, nux, nuy, W);
             if (!__all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext))) break;
             finish_row<M, true, true>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
         }
@@ -344,11 +352,12 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         }
     }
     for (; r < jend; ++r) {
-        new_edges<M, WETPATH>(P, G, lane, i, r, W);
+        new_edges<M, WETPATH>(P, G, lane, i, r, j1, sg, nux, nuy, W);
         finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
     }
     const double cx = xedge_in ? nux * W.smx : 0.0, cy = core ? nuy * W.smy : 0.0;
-    cfl = fmax_(cfl, fmax_(cx, cy));
+    const double cc = core ? W.scell : 0.0;
+    cfl = fmax_(cfl, fmax_(fmax_(cx, cy), cc));
 }
 
 // Wavefront epilogue: Courant number and counters of the launch.

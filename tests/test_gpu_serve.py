@@ -137,22 +137,24 @@ def test_on_done_reports_every_request_once(S):
     assert all(f > 0.0 for f in fin)
 
 
-def test_blown_up_scenario_fails_fast_and_the_rest_complete(S):
-    """Basin seed 1114 on a 1414^2 grid: after ~1800 steps the wall treatment
-    at the shoreline leaves a millimetre-thin layer moving at hundreds of m/s
-    and the time step collapses (the oracle does the same, byte for byte).
-    The run must end with SWE_E_CFL within seconds, and a request served
-    beside it must complete normally."""
+def test_shoreline_thin_layer_scenario_completes(S):
+    """Basin seed 1114 on a 1414^2 grid with the serving workload's
+    parameters: after ~1800 steps the drawdown at the shoreline wall leaves a
+    millimetre-thin layer moving at hundreds of m/s.  With the cells' own
+    speeds in the Courant number the time step shrinks while the layer drains
+    and the run completes (with Roe edge speeds alone it blew up); a request
+    served beside it completes as well."""
     import time
     b = I.basin(1414, 1114)
     g = S.Grid(1414, 1414, b.grid.dx, b.grid.dy)
-    bad = S.Request(g, S.Params(), b.B, b.eta0, b.target, 0.0, 3600.0, 7200.0, 32, 1e-4, flag_every=4)
+    thin = S.Request(g, S.Params(), b.B, b.eta0, b.target, 0.0, 3600.0, 7200.0, 32, 1e-4, flag_every=4)
     good, _ = make_request(S, 96, 1003)
-    arena = arena_for(S, [bad, good], copies=2)
+    arena = arena_for(S, [thin, good], copies=2)
     t = time.perf_counter()
-    rc, st = S.serve([bad, good], arena, 2, check=False)
+    rc, st = S.serve([thin, good], arena, 2, check=False)
     el = time.perf_counter() - t
-    print(f"blown-up scenario: status {st[0]['status']} after {el:.1f} s; beside it: {st[1]['status']}")
-    assert st[0]["status"] == S.E_CFL and rc == S.E_CFL
-    assert st[1]["status"] == 0 and st[1]["n_fwd_steps"] > 0
+    print(f"thin-layer scenario: status {st[0]['status']}, {st[0]['n_fwd_steps']} forward steps, "
+          f"{el:.1f} s; beside it: {st[1]['status']}")
+    assert rc == 0 and st[0]["status"] == 0 and st[1]["status"] == 0
+    assert st[0]["n_fwd_steps"] > 2000
     assert el < 60.0
