@@ -41,6 +41,42 @@ def test_lake_at_rest_bit_exact(oracle):
     assert np.all(hu == 0.0) and np.all(hv == 0.0)
 
 
+def test_courant_number_counts_thin_fast_layer(oracle):
+    """The Courant number of the nonlinear step (reading R29): the largest of
+    nu|s| over the edges and nu_x(|u| + sqrt(g) sqrt(h)), nu_y(|v| + ...) over
+    the wet interior cells.  A millimetre layer moving at 600 m/s next to a
+    dry cell: the Roe averages of its edges are slow, its own speed is not, so
+    the cell term is the maximum, in closed form.  On a lake at rest the edge
+    speeds sqrt(g hbar) never exceed the deepest cell's sqrt(g) sqrt(h) by
+    more than rounding."""
+    O = oracle
+    g = O.Grid(8, 6, 500.0, 700.0, 0.0, 0.0, (0, 0, 0, 0))
+    p = O.Params()
+    B = np.full((6, 8), -5.0)
+    B[:, 6:] = 2.0                                  # dry land east of column 5
+    h = np.maximum(0.0, -B)
+    hu = np.zeros_like(h)
+    hv = np.zeros_like(h)
+    h[3, 5] = 0.004
+    hu[3, 5] = -2.4                                 # u = -600 m/s, moving off the shore
+    dt = 0.05
+    _, _, _, cfl, _ = O.swe_step(g, p, B, h, hu, hv, dt)
+    cell = (dt / 500.0) * (abs(hu[3, 5] / h[3, 5]) + math.sqrt(9.81) * math.sqrt(h[3, 5]))
+    assert cfl == cell
+    # the edges alone would not see it: Roe speeds of its edges stay far below
+    hl = h[3, 4]
+    uroe = (math.sqrt(hl) * 0.0 + math.sqrt(0.004) * -600.0) / (math.sqrt(hl) + math.sqrt(0.004))
+    assert (dt / 500.0) * (abs(uroe) + math.sqrt(9.81 * 0.5 * (hl + 0.004))) < 0.2 * cell
+    # lake at rest: the maximum is the deepest cell's sqrt(g) sqrt(h) term or an
+    # edge's sqrt(g hbar), equal up to rounding
+    B2 = -np.linspace(10.0, 40.0, 48).reshape(6, 8)
+    h2 = -B2
+    z = np.zeros_like(h2)
+    _, _, _, cfl2, _ = O.swe_step(g, p, B2, h2, z, z, dt)
+    ref = max(dt / 500.0, dt / 700.0) * math.sqrt(9.81) * math.sqrt(h2.max())
+    assert abs(cfl2 - ref) <= 1e-14 * ref
+
+
 def test_lake_at_rest_first_order_no_transverse(oracle):
     """Same at first order without transverse terms."""
     O = oracle
