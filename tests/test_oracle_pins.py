@@ -172,6 +172,59 @@ def test_reflection_transmission_at_depth_step(oracle):
     assert abs(trans - Tr) / Tr < 0.01
 
 
+def _golden(name):
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                vals[k] = float(v)
+    return vals
+
+
+def test_paper_1d_example_split_reflect_transmit(oracle):
+    """The paper's 1D example (Sec. 3; configuration in
+    tests/golden/sec3_1d_step_example.txt): the stationary 0.4 m hump splits
+    into two 0.2 m waves (d'Alembert); the shoreward one meets the
+    4000 m -> 200 m step and leaves a reflected wave of 0.2 R and a
+    transmitted wave of 0.2 T, R = (c1-c2)/(c1+c2), T = 2c1/(c1+c2).  At
+    t = 700 s the three waves are apart and none has reached a wall."""
+    O = oracle
+    gd = _golden("sec3_1d_step_example.txt")
+    n = 4000
+    L = gd["x_max"] - gd["x_min"]
+    dx = L / n
+    x = gd["x_min"] + (np.arange(n) + 0.5) * dx
+    B = np.where(x <= gd["shelf_edge"], -gd["depth_shelf"], -gd["depth_ocean"])
+    eta = gd["hump_height"] * np.exp(-((x - gd["hump_centre"]) / gd["hump_halfwidth"]) ** 2)
+    mu = np.zeros(n)
+    g = O.Grid(n, 1, dx, 1.0, gd["x_min"])
+    p = O.Params()
+    c1, c2 = math.sqrt(G * gd["depth_ocean"]), math.sqrt(G * gd["depth_shelf"])
+    T = 700.0
+    ns = int(math.ceil(T / (0.9 * dx / c1)))
+    dt = T / ns
+    for _ in range(ns):
+        eta, mu, _ = O.lin_step(g, p, B, eta, mu, dt)
+    R, Tr = (c1 - c2) / (c1 + c2), 2 * c1 / (c1 + c2)
+    a = 0.5 * gd["hump_height"]
+    t_hit = (gd["hump_centre"] - gd["shelf_edge"]) / c1
+    x_out = gd["hump_centre"] + c1 * T
+    x_ref = gd["shelf_edge"] + c1 * (T - t_hit)
+    x_tr = gd["shelf_edge"] - c2 * (T - t_hit)
+    # the transmitted wave is squeezed by c2/c1 on the shelf (~22 cells a
+    # half-width), so its peak is resolved less finely than the others
+    for xc, amp, rel in ((x_out, a, 0.002), (x_ref, a * R, 0.002), (x_tr, a * Tr, 0.015)):
+        win = np.abs(x - xc) < 20e3
+        peak = eta[win].max()
+        assert abs(peak - amp) / amp < rel, (xc, peak, amp)
+        assert abs(x[win][np.argmax(eta[win])] - xc) < 1.5e3
+    # mass: the linear update conserves the sum of eta
+    assert abs(eta.sum() - (gd["hump_height"] * np.exp(
+        -((np.arange(n) * dx + 0.5 * dx - gd["hump_centre"]) / gd["hump_halfwidth"]) ** 2)).sum()) < 1e-9
+
+
 # --------------------------------------------------------------------------
 # nonlinear solver: Stoker's wet-bed dam break (exact Riemann solution)
 # --------------------------------------------------------------------------
