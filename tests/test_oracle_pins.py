@@ -225,6 +225,45 @@ def test_paper_1d_example_split_reflect_transmit(oracle):
         -((np.arange(n) * dx + 0.5 * dx - gd["hump_centre"]) / gd["hump_halfwidth"]) ** 2)).sum()) < 1e-9
 
 
+def test_paper_1d_target_duality(oracle):
+    """The paper's 1D example with its target (Sec. 3, eq. phi_1d; fixtures
+    sec3_1d_step_example.txt and sec3_1d_target.txt): J = int over 10..25 km
+    of eta(x, t_f), t_f = 4200 s.  At first order with walls the adjoint step
+    is the transpose of the forward one, so J from the forward run equals
+    <q~(t_f), q(0)> from the adjoint run to rounding; the waves in the
+    target interval at t_f make J clearly non-zero."""
+    O = oracle
+    gd = _golden("sec3_1d_step_example.txt")
+    tg = _golden("sec3_1d_target.txt")
+    n = 800
+    L = gd["x_max"] - gd["x_min"]
+    dx = L / n
+    x = gd["x_min"] + (np.arange(n) + 0.5) * dx
+    B = np.where(x <= gd["shelf_edge"], -gd["depth_shelf"], -gd["depth_ocean"])
+    eta0 = gd["hump_height"] * np.exp(-((x - gd["hump_centre"]) / gd["hump_halfwidth"]) ** 2)
+    g = O.Grid(n, 1, dx, 1.0, gd["x_min"])
+    p = O.Params(order=1)
+    xc = 0.5 * (tg["target_from"] + tg["target_to"])
+    R = 0.5 * (tg["target_to"] - tg["target_from"])
+    phi = O.target(g, p, B, xc, 0.0, R, O.DISK).ravel()
+    # the indicator of the interval, in the cells whose centres lie in it
+    assert np.array_equal(phi > 0, (x >= tg["target_from"]) & (x <= tg["target_to"]))
+    ns, dt = O.adj_nsub(g, p, B, 0.0, tg["t_f"], 1)
+    e, m = eta0.copy(), np.zeros(n)
+    for _ in range(ns):
+        e, m, _ = O.lin_step(g, p, B, e, m, dt)
+    J_fwd = (phi * e).sum() * dx
+    a0, a1 = phi.copy(), np.zeros(n)
+    for _ in range(ns):
+        a0, a1, _, _ = O.adj_step(g, p, B, a0, a1, None, dt)
+        a0, a1 = a0.ravel(), a1.ravel()
+    J_adj = ((a0 * eta0).sum() + (a1 * 0.0).sum()) * dx
+    assert abs(J_fwd - J_adj) <= 1e-12 * abs(J_fwd)
+    # waves are in the interval at t_f (the hump's shoreward half, transmitted
+    # onto the shelf and reflected at the shore): the check is not vacuous
+    assert abs(J_fwd) > 0.01 * (tg["target_to"] - tg["target_from"])
+
+
 # --------------------------------------------------------------------------
 # nonlinear solver: Stoker's wet-bed dam break (exact Riemann solution)
 # --------------------------------------------------------------------------
