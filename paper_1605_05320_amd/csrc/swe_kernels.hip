@@ -417,7 +417,9 @@ __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L,
     G.base = pt.offset;
     const int rows = L.pass_rows[pass];
     const int row0 = L.pass_row0 ? L.pass_row0[pass] : 0;
-    march<M, false, false>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
+    // all-wet fast path, not the subcritical one (that spills here: the lane's
+    // patch geometry takes registers the uniform grid keeps in scalars)
+    march<M, true, false>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
              pt.dx, pt.dy, cfl, nclamp, nbad);
 }
 
