@@ -286,7 +286,9 @@ typedef enum {
  *   pass_rows, pass_row0: n_passes int32;  job_pass: n_jobs+1 int32 (passes of
  *              job j are job_pass[j] .. job_pass[j+1]-1)
  * Call with null outputs to get the sizes.  Returns n_passes (>= 0) and sets
- * *n_jobs, or a negative swe_status.  patches: host array.
+ * *n_jobs, or a negative swe_status (SWE_E_INVAL for a patch with nx or ny
+ * < 2, offset < 0, dx or dy <= 0, or a bc[k] that is not a swe_bc).
+ * patches: host array.
  */
 SWE_API int32_t swe_level_schedule(const swe_patch *patches, int32_t n_patches, int32_t kind, int32_t chunk_rows,
                                    int64_t *lanes, int32_t *pass_rows, int32_t *pass_row0, int32_t *job_pass,

@@ -413,13 +413,11 @@ __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L,
     const swe_patch pt = L.patches[patch];
     Geo G;
     G.nx = pt.nx; G.ny = pt.ny; G.pitch = pt.nx;
-    G.bc[0] = pt.bc[0]; G.bc[1] = pt.bc[1]; G.bc[2] = pt.bc[2]; G.bc[3] = pt.bc[3];
+    G.bcm = pack_bc(pt.bc);
     G.base = pt.offset;
     const int rows = L.pass_rows[pass];
     const int row0 = L.pass_row0 ? L.pass_row0[pass] : 0;
-    // all-wet fast path, not the subcritical one (that spills here: the lane's
-    // patch geometry takes registers the uniform grid keeps in scalars)
-    march<M, true, false>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
+    march<M, true, true>(P, G, lane, col, row0, min(row0 + rows, pt.ny), row0 + rows, (role & 1) != 0, (role & 2) != 0,
              pt.dx, pt.dy, cfl, nclamp, nbad);
 }
 

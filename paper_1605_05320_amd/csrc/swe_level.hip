@@ -63,6 +63,10 @@ int32_t swe_level_schedule(const swe_patch *patches, int32_t n, int32_t kind, in
         if (patches[p].nx < 2 || patches[p].ny < 2 || patches[p].offset < 0 || !(patches[p].dx > 0.0) ||
             !(patches[p].dy > 0.0))
             return fail(SWE_E_INVAL, "patch %d: need nx, ny >= 2, offset >= 0, dx, dy > 0", p);
+    for (int p = 0; p < n; ++p)
+        for (int k = 0; k < 4; ++k)
+            if (patches[p].bc[k] != SWE_BC_WALL && patches[p].bc[k] != SWE_BC_EXTRAP)
+                return fail(SWE_E_INVAL, "patch %d: bc[%d] = %d is not a boundary condition", p, k, patches[p].bc[k]);
 
     // jobs: lists of passes; a patch never spans two jobs
     std::vector<std::vector<Pass>> jobs;

@@ -80,3 +80,8 @@ def test_schedule_rejects_bad_input(S):
     tab, _ = S.patch_table([1], [8], [100.0])
     with pytest.raises(S.SweError):
         S.level_schedule(tab, 1)
+    tab, _ = S.patch_table([8, 8], [8, 8], [100.0, 100.0])
+    S.level_schedule(tab, 1)
+    tab[1].bc[2] = 2      # neither wall nor extrapolation
+    with pytest.raises(S.SweError, match="bc"):
+        S.level_schedule(tab, 1)
