@@ -60,6 +60,9 @@ typedef enum {
     SWE_E_NEGDEPTH = -6    /* a negative depth had to be clamped */
 } swe_status;
 
+/* Largest nx of a grid (a row of one plane then spans < 2 GiB). */
+#define SWE_MAX_NX (1 << 27)
+
 typedef enum { SWE_BC_WALL = 0, SWE_BC_EXTRAP = 1 } swe_bc;
 typedef enum { SWE_NONLINEAR = 0, SWE_LINEAR = 1 } swe_model;
 typedef enum { SWE_TARGET_GAUSS = 0, SWE_TARGET_DISK = 1 } swe_target_shape;

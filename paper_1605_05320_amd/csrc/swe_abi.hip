@@ -95,6 +95,8 @@ swe_status check_grid(const swe_grid *g)
     if (g->nx < 2) return fail(SWE_E_INVAL, "nx = %d < 2", g->nx);
     if (g->ny < 1) return fail(SWE_E_INVAL, "ny = %d < 1", g->ny);
     if (g->pitch < g->nx) return fail(SWE_E_INVAL, "pitch %d < nx %d", g->pitch, g->nx);
+    // a row's bytes must fit the 32-bit range of the step kernel's row stores
+    if (g->nx > SWE_MAX_NX) return fail(SWE_E_INVAL, "nx = %d > %d", g->nx, SWE_MAX_NX);
     if ((long long)g->ny * g->pitch > (1LL << 40)) return fail(SWE_E_INVAL, "grid too large");
     if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(SWE_E_INVAL, "dx must be > 0");
     if (g->ny > 1 && (!(g->dy > 0.0) || !std::isfinite(g->dy))) return fail(SWE_E_INVAL, "dy must be > 0");

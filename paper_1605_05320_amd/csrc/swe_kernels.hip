@@ -143,19 +143,46 @@ struct Window {
     RawCell rE;              // stored values of row r + 3, loaded one row ahead
     double smx, smy;         // largest |s| of the counted x- and y-edges
     double scell;            // largest cell term of the Courant number (rows j0 .. j1-1)
+    double o[3];             // updated row, stored at the start of the next row
+    bool ost;                //   by this lane
     // the edge carries no waves on any lane of the wavefront (sea at rest)
     bool zyS, zyN, zxCur, zyNN, zxNext;
 };
+
+// Stores of row r through buffer resources that cover exactly that row's
+// cells (rows are wave-uniform on the uniform grid): lanes with st false get
+// an offset beyond the resource and their stores are dropped, so the stores
+// need no branch around them (loads and stores share one memory counter; a
+// branch would merge counter states with and without the stores, and waits
+// for later loads would then wait for the stores as well).  With st false on
+// every lane, r is not used.
+__device__ __forceinline__ void store_row_buffer(const KParams &P, int r, int i, bool st, const double (&o)[3])
+{
+    const size_t row = (size_t)(r > 0 ? r : 0) * P.pitch;
+    const int nbytes = P.nx * (int)sizeof(double);
+    const int off = st ? i * (int)sizeof(double) : 0x7ffffff8;
+    double *planes[3] = {P.out0, P.out1, P.out2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(planes[c] + row, 0, nbytes, BUF_WORD3);
+        const unsigned long long b = (unsigned long long)__double_as_longlong(o[c]);
+        const unsigned int v __attribute__((ext_vector_type(2))) = {(unsigned int)b, (unsigned int)(b >> 32)};
+        __builtin_amdgcn_raw_buffer_store_b64(v, rs, off, 0, 0);
+    }
+}
 
 // Row r, first part: row r + 2's cell data and the waves of the row's two
 // new edges (y-edge r + 3/2, x-edge (i - 1/2, r + 1)), without the wall and
 // dry-edge cases when all their cells are wet on every lane (lane 0's x-edge,
 // whose west cell is a zero fill, reaches no result and is not asked).
-template <class M, bool WETPATH>
+template <class M, bool WETPATH, bool BUFST>
 __device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int lane, int i, int r, int j1, double sg,
                                           double nux, double nuy, Window<M> &W)
 {
     W.cE = M::cell(P, W.rE);
+    // row r - 1 goes out just before row r + 3's loads: both then have this
+    // row's work to complete in before anything waits for them
+    if (BUFST) store_row_buffer(P, r - 1, i, W.ost, W.o);
     W.rE = M::raw(P, G, i, r + 3);                 // in flight during this row
     if (r + 2 < j1) W.scell = fmax_(W.scell, M::cell_cfl(W.cE, sg, nux, nuy));
     typename M::Cell lD = M::lo_cell(W.cD);
@@ -173,7 +200,7 @@ __device__ __forceinline__ void new_edges(const KParams &P, const Geo &G, int la
 // Row r, second part: fluctuations of the new edges, correction fluxes,
 // update and store of row r, then the window moves down one row.  SUB_NEW:
 // sub_edge holds for the new edges on every lane; SUB: for yN and xCur.
-template <class M, bool SUB_NEW, bool SUB>
+template <class M, bool SUB_NEW, bool SUB, bool BUFST>
 __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i, int r, bool row_ok, bool core,
                                            double nux, double nuy, double hnux, double hnuy, Window<M> &W,
                                            int &nclamp, int &nbad)
@@ -199,8 +226,8 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
 #pragma unroll
     for (int c = 0; c < 3; ++c) F_E[c] = from_hi(F_W[c]);
 
+    double o[3] = {0.0, 0.0, 0.0};
     if (core && row_ok) {
-        double o[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             double qv = W.qC.q[c];
@@ -218,10 +245,17 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
             if (o[0] < 0.0) { o[0] = 0.0; ++nclamp; }
         }
         if (!isfinite(o[0]) || !isfinite(o[1]) || !isfinite(o[2])) ++nbad;
-        size_t k = (size_t)(G.base + (long long)r * G.pitch + i);
-        P.out0[k] = o[0];
-        P.out1[k] = o[1];
-        P.out2[k] = o[2];
+        if (!BUFST) {
+            size_t k = (size_t)(G.base + (long long)r * G.pitch + i);
+            P.out0[k] = o[0];
+            P.out1[k] = o[1];
+            P.out2[k] = o[2];
+        }
+    }
+    if (BUFST) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) W.o[c] = o[c];
+        W.ost = core && row_ok;
     }
     if (row_ok) {
 #pragma unroll
@@ -257,7 +291,7 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
 // runs the general forms.  The Courant number is nu max|s| over the edges,
 // which equals the largest nu|s| exactly (rounding is monotonic), and the
 // cells' own terms (nonlinear model) over the march's rows.
-template <class M, bool WETPATH = true, bool SUBPATH = true>
+template <class M, bool WETPATH = true, bool SUBPATH = true, bool BUFST = false>
 __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
                                       int jend, bool core, bool xedge_in, double dx, double dy,
                                       double &cfl, int &nclamp, int &nbad)
@@ -271,11 +305,14 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     W.smy = 0.0;
     W.scell = 0.0;
     {
-        Cell cA = M::load(P, G, i, j0 - 2);
-        Cell cB = M::load(P, G, i, j0 - 1);
-        Cell cC = M::load(P, G, i, j0);
-        W.cD = M::load(P, G, i, j0 + 1);
+        // all five rows' loads in flight before the first is used
+        const RawCell rA = M::raw(P, G, i, j0 - 2), rB = M::raw(P, G, i, j0 - 1), rC = M::raw(P, G, i, j0),
+                      rD = M::raw(P, G, i, j0 + 1);
         W.rE = M::raw(P, G, i, j0 + 2);
+        Cell cA = M::cell(P, rA);
+        Cell cB = M::cell(P, rB);
+        Cell cC = M::cell(P, rC);
+        W.cD = M::cell(P, rD);
         if (j0 < j1) W.scell = fmax_(W.scell, M::cell_cfl(cC, sg, nux, nuy));
         if (j0 + 1 < j1) W.scell = fmax_(W.scell, M::cell_cfl(W.cD, sg, nux, nuy));
         Edge yS2, yS0, xPrev;
@@ -338,23 +375,33 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         keep_yprev<M>(yS0, W.yS);
         keep_qrow<M>(cC, W.qC);
     }
+    W.ost = false;
+    W.o[0] = 0.0; W.o[1] = 0.0; W.o[2] = 0.0;
 
+    // One exit, at the latch (an exit between a row's loads and its stores
+    // makes the compiler join the two ways before the back-edge, and the
+    // waits it places there then cover the stores just issued).
     int r = j0;
-    if (SUBPATH && __all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
-        for (; r < jend; ++r) {
-            new_edges<M, WETPATH>(P, G, lane, i, r, j1, sg, nux, nuy, W);
-            if (!__all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext))) break;
-            finish_row<M, true, true>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
-        }
+    if (SUBPATH && r < jend && __all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
+        bool sub_new;
+        do {
+            new_edges<M, WETPATH, BUFST>(P, G, lane, i, r, j1, sg, nux, nuy, W);
+            sub_new = __all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext));
+            if (sub_new) {
+                finish_row<M, true, true, BUFST>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
+                ++r;
+            }
+        } while (sub_new && r < jend);
         if (r < jend) {            // the row whose new edges ended the loop
-            finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
+            finish_row<M, false, false, BUFST>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
             ++r;
         }
     }
     for (; r < jend; ++r) {
-        new_edges<M, WETPATH>(P, G, lane, i, r, j1, sg, nux, nuy, W);
-        finish_row<M, false, false>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
+        new_edges<M, WETPATH, BUFST>(P, G, lane, i, r, j1, sg, nux, nuy, W);
+        finish_row<M, false, false, BUFST>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
     }
+    if (BUFST) store_row_buffer(P, r - 1, i, W.ost, W.o);   // the last row
     const double cx = xedge_in ? nux * W.smx : 0.0, cy = core ? nuy * W.smy : 0.0;
     const double cc = core ? W.scell : 0.0;
     cfl = fmax_(cfl, fmax_(fmax_(cx, cy), cc));
@@ -389,7 +436,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_march2d(KParams P)
     const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
     double cfl = 0.0;
     int nclamp = 0, nbad = 0;
-    march<M>(P, uniform_geo(P), lane, i, j0, j1, j1, core, xedge_in, P.dx, P.dy, cfl, nclamp, nbad);
+    march<M, true, true, true>(P, uniform_geo(P), lane, i, j0, j1, j1, core, xedge_in, P.dx, P.dy, cfl, nclamp,
+                               nbad);
     march_epilogue(P, lane, cfl, nclamp, nbad);
 }
 
