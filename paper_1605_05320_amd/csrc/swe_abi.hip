@@ -52,40 +52,53 @@ int wave_slots()
     return slots;
 }
 
-// Rows marched per wavefront.  The smallest height of at least 2 rows whose
-// launch fits in one wave of resident wavefronts (a march's time is its rows
-// plus a warm-up of about 2.5 rows, so while the launch fits, shorter marches
+// Rows marched per wavefront: ly, and ly + 1 for the first lyr chunks of a
+// strip.  While the launch fits in one wave of resident wavefronts, the most
+// chunks that fit, with at least 2 rows each (a march's time is its rows plus
+// a warm-up of about 2.5 rows, so while the launch fits, shorter marches
 // finish sooner: measured 11.5 us at 2 rows against 24.6 us at 8 rows on a
-// 256^2 grid, 20.0 us at 3 rows against 25.7 us at 8 on 512^2); 24 when the
-// grid is too large for that (measured best of 16 to 64 rows on a 4096^2
-// grid).
-// SWE_MARCH_ROWS overrides it (tuning sweeps).
-int default_ly(int nx, int ny)
+// 256^2 grid, 20.0 us at 3 rows against 25.7 us at 8 on 512^2).  Filling the
+// slots puts two wavefronts on every SIMD; with fewer, some SIMDs hold one
+// and finish early while the pairs on the others set the launch's time
+// (measured on 1024^2 with 103 marches of 10 rows per strip: a wavefront
+// alone on its SIMD took 30 us, a pair 30 and 47 us).  Heights differ by at
+// most one row.  24 rows when the grid is too large for one wave of
+// wavefronts (measured best of 16 to 64 rows on a 4096^2 grid).
+// SWE_MARCH_ROWS forces ly rows for every chunk (tuning sweeps).
+void march_rows(int nx, int ny, int &ly, int &lyr)
 {
     static const int forced = [] {
         const char *e = std::getenv("SWE_MARCH_ROWS");
         int v = e ? std::atoi(e) : 0;
         return (v >= 1 && v <= 4096) ? v : 0;
     }();
-    if (forced > 0) return forced;
-    long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
-    for (int ly = 2; ly <= 24; ++ly)
-        if (strips * ((ny + ly - 1) / ly) <= wave_slots()) return ly;
-    return 24;
+    lyr = 0;
+    if (forced > 0) { ly = forced; return; }
+    const long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
+    long long c = std::min<long long>(wave_slots() / strips, ny / 2);
+    if (c < 1 || (ny + c - 1) / c > 24) c = (ny + 23) / 24;
+    ly = (int)(ny / c);
+    lyr = (int)(ny % c);
+}
+
+// Chunks of a strip for march heights ly, lyr.
+int march_chunks(int ny, int ly, int lyr)
+{
+    return lyr > 0 ? (ny - lyr) / ly : (ny + ly - 1) / ly;
 }
 
 // XCD-aware tile placement pays when all wavefronts of the launch are
 // resident together (halo rows then come from the shared L2); for larger
 // launches it concentrates each XCD on a narrow band of memory and is off.
 // SWE_XCD_REMAP=0/1 forces it.
-int xcd_remap_for(int nx, int ny, int ly)
+int xcd_remap_for(int nx, int nchunks)
 {
     static const int forced = [] {
         const char *e = std::getenv("SWE_XCD_REMAP");
         return e ? (std::atoi(e) != 0 ? 1 : 0) : -1;
     }();
     if (forced >= 0) return forced;
-    long long waves = (long long)((nx + swe::STRIP - 1) / swe::STRIP) * ((ny + ly - 1) / ly);
+    long long waves = (long long)((nx + swe::STRIP - 1) / swe::STRIP) * nchunks;
     return waves <= wave_slots() ? 1 : 0;
 }
 
@@ -152,8 +165,9 @@ swe::KParams make_kparams(const swe_grid *g, const swe_params *p, const double *
 {
     swe::KParams k;
     std::memset(&k, 0, sizeof k);
-    k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch; k.ly = default_ly(g->nx, g->ny);
-    k.xcd_remap = xcd_remap_for(g->nx, g->ny, k.ly);
+    k.nx = g->nx; k.ny = g->ny; k.pitch = g->pitch;
+    march_rows(g->nx, g->ny, k.ly, k.lyr);
+    k.xcd_remap = xcd_remap_for(g->nx, march_chunks(g->ny, k.ly, k.lyr));
     for (int c = 0; c < 4; ++c) k.bc[c] = g->bc[c];
     k.order = p->order; k.transverse = p->transverse;
     k.dx = g->dx; k.dy = g->ny > 1 ? g->dy : 1.0; k.dt = dt;

@@ -430,8 +430,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_march2d(KParams P)
     const int t = P.xcd_remap ? xcd_logical_block(blockIdx.x, G) : blockIdx.x;
     const int strip = t / P.nchunks, chunk = t - strip * P.nchunks;
     const int i = strip * STRIP + lane - HALO;
-    const int j0 = chunk * P.ly;
-    const int j1 = min(j0 + P.ly, P.ny);
+    const int j0 = chunk * P.ly + min(chunk, P.lyr);
+    const int j1 = min(j0 + P.ly + (chunk < P.lyr ? 1 : 0), P.ny);
     const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
     const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
     double cfl = 0.0;
@@ -932,7 +932,7 @@ hipError_t launch_step(int model, const KParams &P, hipStream_t s)
     } else {
         KParams Q = P;
         Q.nstrips = (P.nx + STRIP - 1) / STRIP;
-        Q.nchunks = (P.ny + P.ly - 1) / P.ly;
+        Q.nchunks = P.lyr > 0 ? (P.ny - P.lyr) / P.ly : (P.ny + P.ly - 1) / P.ly;
         dim3 grid(Q.nstrips * Q.nchunks);
         if (model == MODEL_NL) hipLaunchKernelGGL(k_march2d<NL>, grid, block, 0, s, Q);
         else if (model == MODEL_ADJ) hipLaunchKernelGGL(k_march2d<ADJ<true>>, grid, block, 0, s, Q);
