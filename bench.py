@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="the full serving workload: 256 requests, grids 256^2..2048^2")
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only (no headline)")
+    ap.add_argument("--busy-only", type=int, default=0, metavar="K",
+                    help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one device copy of known size (HBM counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -146,6 +148,13 @@ def main():
     if args.serve_only:
         print(json.dumps({"serve": serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin,
                                                args.serve_nmax)}), flush=True)
+        return
+    if args.busy_only > 0:
+        g, p, B, qa, qb, dt = busy_state(S, torch, I, np, f64, args.n)
+        for _ in range(args.busy_only):
+            S.swe_step(g, p, B, qa, qb, dt)
+        torch.cuda.synchronize()
+        print(json.dumps({"busy_launches": args.busy_only, "n": args.n}), flush=True)
         return
 
     n = args.n
@@ -259,6 +268,24 @@ def _time_events(torch, fn, reps):
     return a.elapsed_time(z) * 1e-3 / reps
 
 
+def busy_state(S, torch, I, np, f64, n):
+    """The n x n basin (seed 2) with a centimetre of seeded noise on the
+    surface of every wet cell, so that every edge carries waves, and a step
+    at half the desired Courant number."""
+    b = I.basin(n, 2)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **f64)
+    noise = np.random.default_rng(7).uniform(-0.01, 0.01, b.B.shape)
+    qa = [torch.empty(n, n, **f64) for _ in range(3)]
+    qb = [torch.empty(n, n, **f64) for _ in range(3)]
+    S.swe_init(g, p, B, torch.tensor(b.eta0 + noise, **f64), qa)
+    spd = torch.zeros(1, dtype=torch.int64, device=B.device)
+    S.swe_max_speed(g, p, B, qa, 0, spd)
+    dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
+    return g, p, B, qa, qb, dt
+
+
 def secondary(S, torch, I, np, f64):
     out = {}
     # adjoint step at 1024^2 (linearized, f-wave, transverse)
@@ -314,7 +341,7 @@ def secondary(S, torch, I, np, f64):
     spd = torch.zeros(1, dtype=torch.int64, device=B.device)
     S.swe_max_speed(g, p, B, qa, 0, spd)
     dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
-    t = _time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), 40)
+    t = min(_time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), 40) for _ in range(3))
     out["step_4096_cell_updates_per_s"] = n * n / t
     out["step_4096_us"] = t * 1e6
     out["step_4096_algorithmic_GBs"] = BYTES_PER_CELL_STEP * n * n / t / 1e9
@@ -323,21 +350,11 @@ def secondary(S, torch, I, np, f64):
     # the step with waves on every edge (noise on the surface of every wet
     # cell), so that no row of sea at rest is skipped
     for n, reps in ((1024, 100), (4096, 20)):
-        b = I.basin(n, 2)
-        g = S.Grid(n, n, b.grid.dx, b.grid.dy)
-        B = torch.tensor(b.B, **f64)
-        noise = np.random.default_rng(7).uniform(-0.01, 0.01, b.B.shape)
-        e = torch.tensor(b.eta0 + noise, **f64)
-        qa = [torch.empty(n, n, **f64) for _ in range(3)]
-        qb = [torch.empty(n, n, **f64) for _ in range(3)]
-        S.swe_init(g, p, B, e, qa)
-        spd = torch.zeros(1, dtype=torch.int64, device=B.device)
-        S.swe_max_speed(g, p, B, qa, 0, spd)
-        dt = 0.5 * p.cfl_desired / float(spd.view(torch.float64).item())
+        g, p, B, qa, qb, dt = busy_state(S, torch, I, np, f64, n)
         t = min(_time_events(torch, lambda: S.swe_step(g, p, B, qa, qb, dt), reps) for _ in range(3))
         out[f"step_busy_{n}_cell_updates_per_s"] = n * n / t
         out[f"step_busy_{n}_us"] = t * 1e6
-        del qa, qb, B, e
+        del qa, qb, B
         torch.cuda.empty_cache()
     out.update(run_bench(S, torch, I, np, f64))
     out.update(level_bench(S, torch, I, np, f64))

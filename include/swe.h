@@ -81,9 +81,9 @@ typedef struct {
     int32_t order;          /* 1 (Godunov) or 2 (MC-limited corrections) */
     int32_t transverse;     /* 1: transverse splitting of fluctuations (2D) */
     int32_t reserved;
-    double g;               /* gravity (m/s^2) */
+    double g;               /* gravity (m/s^2), in [1e-100, 1e100] */
     double sea_level;       /* eta_bar: the surface the equations are linearized about */
-    double dry_tol;         /* a cell is wet iff its depth > dry_tol (m) */
+    double dry_tol;         /* a cell is wet iff its depth > dry_tol (m), in [1e-100, 1e100] */
     double cfl_desired;     /* target Courant number of the variable time step */
     double cfl_max;         /* steps with a larger Courant number are rejected */
 } swe_params;

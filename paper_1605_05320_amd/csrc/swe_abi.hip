@@ -124,8 +124,8 @@ swe_status check_params(const swe_params *p)
     if (!p) return fail(SWE_E_INVAL, "params is NULL");
     if (p->order != 1 && p->order != 2) return fail(SWE_E_INVAL, "order must be 1 or 2");
     if (p->transverse != 0 && p->transverse != 1) return fail(SWE_E_INVAL, "transverse must be 0 or 1");
-    if (!(p->g > 0.0)) return fail(SWE_E_INVAL, "g must be > 0");
-    if (!(p->dry_tol >= 0.0)) return fail(SWE_E_INVAL, "dry_tol must be >= 0");
+    if (!swe::params_in_range(p))
+        return fail(SWE_E_INVAL, "g = %g and dry_tol = %g must lie in [1e-100, 1e100]", p->g, p->dry_tol);
     if (!std::isfinite(p->sea_level)) return fail(SWE_E_INVAL, "sea_level must be finite");
     if (p->model != SWE_NONLINEAR && p->model != SWE_LINEAR) return fail(SWE_E_INVAL, "unknown model");
     return SWE_OK;

@@ -51,6 +51,14 @@ struct CellParams {
 // record a message for swe_last_error() and return st
 swe_status fail(swe_status st, const char *fmt, ...);
 
+// g and dry_tol lie in [1e-100, 1e100]: the step kernels' square roots and
+// divisions of depths and wave speeds rely on operands far from the ends of
+// the double range.
+inline bool params_in_range(const swe_params *p)
+{
+    return p->g >= 1e-100 && p->g <= 1e100 && p->dry_tol >= 1e-100 && p->dry_tol <= 1e100;
+}
+
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
 hipError_t launch_surface_flag(const CellParams &C, const double *q0, double tol, int nonlinear, int8_t *flags,

@@ -184,6 +184,8 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
         (prm->transverse != 0 && prm->transverse != 1) || !(prm->cfl_desired > 0.0) ||
         !(prm->cfl_max >= prm->cfl_desired))
         return fail(SWE_E_INVAL, "bad parameters (nonlinear model, order, transverse, 0 < cfl_desired <= cfl_max)");
+    if (!swe::params_in_range(prm))
+        return fail(SWE_E_INVAL, "g = %g and dry_tol = %g must lie in [1e-100, 1e100]", prm->g, prm->dry_tol);
     if (persistent && !L->sync) return fail(SWE_E_INVAL, "persistent mode needs the sync words");
     if (persistent && L->chunk_rows > 0)
         return fail(SWE_E_INVAL, "persistent mode needs whole-patch jobs (chunk_rows = 0)");

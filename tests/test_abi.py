@@ -139,3 +139,23 @@ def test_serve_rejects_bad_config_before_touching_the_device(S):
     cfg = S.swe_serve_config(256, 1 << 30, 2, 1)
     assert S.lib().swe_serve(arr, 2, C.byref(cfg), st) == S.E_INVAL
     assert "arrival" in S.lib().swe_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [("g", 0.0), ("g", 1e101), ("dry_tol", 0.0), ("dry_tol", 1e-101),
+                                         ("dry_tol", float("nan"))])
+def test_step_rejects_parameters_out_of_range_before_touching_the_device(S, field, value):
+    """g and dry_tol outside [1e-100, 1e100] are argument errors (the step
+    kernels' square roots and divisions rely on that range); the check comes
+    before any device call, so host buffers stand in for the planes."""
+    import torch
+    g = S.Grid(8, 8, 1.0, 1.0)
+    prm = S.Params()
+    setattr(prm, field, value)
+    B = torch.zeros(64, dtype=torch.float64)
+    qa = [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    qb = [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    null_stream = type("NullStream", (), {"cuda_stream": 0})()
+    with pytest.raises(S.SweError) as e:
+        S.swe_step(g, prm, B, qa, qb, 0.1, stream=null_stream)
+    assert e.value.status == S.E_INVAL
+    assert "1e-100" in S.lib().swe_last_error().decode()
