@@ -83,6 +83,39 @@ def traffic_from(fetch_dir: str, write_dir: str, n: int):
     print(json.dumps(out, indent=1))
 
 
+# VALU issue peak: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD
+# every 4 cycles (16 lanes wide); for FP64 FMAs that is the published 78.6
+# TFLOP/s (x 64 lanes x 2 flops).
+VALU_PEAK_G = 256 * 4 * 2.4 / 4
+
+
+def valu_from(sq_dir: str, n: int):
+    """VALU wave-instructions per step-kernel launch from an SQ_INSTS_VALU
+    counter run of 'bench.py --busy-only 10 --n 1024' (the step with waves on
+    every edge)."""
+    rows = _counter_rows(sq_dir, "SQ_INSTS_VALU")
+    step = [float(r["Counter_Value"]) for r in rows if STEP_KERNEL in r["Kernel_Name"]]
+    out = {"kernel": "k_march2d<NL> (order 2, transverse)", "kernel_source_sha": kernel_source_hash(),
+           "workload": f"{n}x{n} synthetic basin, seed 2, a centimetre of noise on every wet cell",
+           "launches": len(step), "valu_instr_per_launch": sum(step) / len(step)}
+    path = os.path.join(ROOT, "profiles", "step_nl_1024_valu.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def load_valu():
+    """VALU instructions per launch of the busy 1024^2 step from the committed
+    counter summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "step_nl_1024_valu.json")) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    return d.get("valu_instr_per_launch") if d.get("kernel_source_sha") == kernel_source_hash() else None
+
+
 def load_traffic(kind: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel source; else None."""
@@ -116,6 +149,9 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="the full serving workload: 256 requests, grids 256^2..2048^2")
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only (no headline)")
+    ap.add_argument("--valu-from", metavar="SQ_DIR",
+                    help="no GPU: read a rocprofv3 --pmc SQ_INSTS_VALU output of 'bench.py --busy-only 10' "
+                         "and write profiles/step_nl_1024_valu.json")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
                     help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -127,6 +163,9 @@ def main():
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(*args.traffic_from, n=args.n)
+        return
+    if args.valu_from:
+        valu_from(args.valu_from, n=args.n)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -225,6 +264,16 @@ def main():
              "wall_s": round(t_wall, 4), "graph_chunk": chunk}
     if not args.no_extra:
         extra.update(secondary(S, torch, I, np, f64))
+        # the VALU-issue roofline of the same kernel on the step with waves on
+        # every edge: counted instructions per launch over the live duration
+        vi = load_valu()
+        if vi is not None and n == 1024:
+            us = extra["step_busy_1024_us"]
+            ach = vi / (us * 1e-6) / 1e9
+            roofline["valu"] = {"bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_G,
+                                "unit": "G VALU wave-instr/s", "frac": round(ach / VALU_PEAK_G, 4),
+                                "case": "1024x1024, waves on every edge", "kernel_avg_us": round(us, 3),
+                                "valu_instr_per_launch": vi}
         extra["serve"] = serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin, args.serve_nmax)
 
     if args.copy_probe:
