@@ -558,15 +558,16 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
         S.swe_init(g, prm, B[o:o + n], eta[o:o + n], q)
         S.swe_max_speed(g, prm, B[o:o + n], q, 0, spd)
     dt0 = prm.cfl_desired / float(spd.view(torch.float64).item())
-    levels = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED),
-              S.Level(tab, S.SCHED_PACKED, chunk_rows=16)]
+    chunks = (8, 12, 16, 24, 32)
+    levels = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED)] + \
+        [S.Level(tab, S.SCHED_PACKED, chunk_rows=r) for r in chunks]
     wa = [torch.empty(ncell, **f64) for _ in range(3)]
     wb = [torch.empty(ncell, **f64) for _ in range(3)]
     ref = [torch.empty(ncell, **f64) for _ in range(3)]
     ctl = S.new_ctl()
     mism = torch.zeros(1, dtype=torch.int32, device=B.device)
     entries, best = S.level_tune(levels, prm, B, init, wa, wb, ref, ctl, mism, dt0, 10, ncell)
-    lnames = ["strip", "packed", "packed-16-row-chunks"]
+    lnames = ["strip", "packed"] + [f"packed-{r}-row-chunks" for r in chunks]
     names = {(l, pm): f"{lnames[l]}/{'persistent' if pm else 'launch-per-step'}"
              for l in range(len(levels)) for pm in (0, 1)}
     lv, pers, _ = entries[best]
