@@ -585,6 +585,32 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
     ms = e0.elapsed_time(e1)
     c = S.read_ctl(ctl)
     best_rate = ncell * c.n_accepted / (ms * 1e-3)
+    # the same attempts captured once as one HIP graph and replayed from the
+    # same state (launch-per-step schedules; the persistent kernel is one
+    # launch already): the whole advance is a single launch from the host
+    graph_ms = graph_same = None
+    if not pers:
+        eager = [x.clone() for x in (wb if c.s.cur else wa)]
+        gs = torch.cuda.Stream()
+        gs.wait_stream(torch.cuda.current_stream())
+        lgraph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(lgraph, stream=gs):
+                S.level_advance(levels[lv], prm, B, wa, wb, ctl, n_steps, 0, stream=gs)
+        torch.cuda.current_stream().wait_stream(gs)
+        for k in range(3):
+            wa[k].copy_(init[k])
+        S.swe_ctl_set(ctl, 0.0, dt0, 1.0e300, 0)
+        torch.cuda.synchronize()
+        e0.record()
+        lgraph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / n_steps
+        cg = S.read_ctl(ctl)
+        got = wb if cg.s.cur else wa
+        graph_same = bool(cg.s.n_accepted == c.s.n_accepted and
+                          all(torch.equal(x, y) for x, y in zip(got, eager)))
     # baseline: one launch per patch per step (fixed dt; no level reduction
     # round-trip charged to it)
     views = []
@@ -614,6 +640,7 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
             "level_steps": n_steps, "level_accepted": c.n_accepted,
             "level_cell_updates_per_s": best_rate,
             "level_ms_per_step": ms / n_steps,
+            "level_graph_ms_per_step": graph_ms, "level_graph_result_identical": graph_same,
             "level_baseline_launch_per_patch_ms_per_step": per_patch * 1e3,
             "level_baseline_launch_per_patch_eager_ms_per_step": per_patch_eager * 1e3,
             "level_baseline_cell_updates_per_s": ncell / per_patch,

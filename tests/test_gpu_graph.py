@@ -1,0 +1,114 @@
+"""HIP-graph capture of the device-controlled stepping (the form the headline
+step is timed in) and of a batched level's launch-per-step advance: a graph of
+K attempts, captured once, is replayed several times with eager work and
+synchronisations in between, and the state and control block after every
+replay equal, bit for bit, those of the same attempts issued eagerly."""
+import numpy as np
+import pytest
+
+from paper_1605_05320_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F64 = dict(dtype=torch.float64, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_05320_amd import swe
+    swe.lib()
+    return swe
+
+
+def current(S, ctl, a, b):
+    c = S.read_ctl(ctl)
+    q = b if c.s.cur else a
+    return [x.cpu().numpy().copy() for x in q], (c.s.t, c.s.dt, c.s.n_accepted, c.s.n_rejected, c.cfl_bits)
+
+
+def capture(fn):
+    """fn(stream) recorded into a graph on a side stream."""
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            fn(gs)
+    torch.cuda.current_stream().wait_stream(gs)
+    torch.cuda.synchronize()
+    return graph
+
+
+def check_replays(S, run_eager, run_in_graph, ctl_e, ctl_g, ea, eb, ga, gb, reps=3):
+    graph = capture(run_in_graph)
+    scratch = torch.randn(1 << 16, **F64)
+    for r in range(reps):
+        run_eager()
+        torch.cuda.synchronize()
+        want_q, want_c = current(S, ctl_e, ea, eb)
+        graph.replay()
+        # the program's own eager work between replays
+        scratch.mul_(1.0001).add_(float(r))
+        torch.cuda.synchronize()
+        got_q, got_c = current(S, ctl_g, ga, gb)
+        print(f"replay {r}: t = {got_c[0]:.3f}, accepted {got_c[2]}, rejected {got_c[3]}")
+        assert got_c == want_c, (r, got_c, want_c)
+        for x, y in zip(got_q, want_q):
+            assert np.array_equal(x, y), r
+
+
+@pytest.mark.parametrize("n,ny,K", [(200, 150, 7), (1024, 1024, 10)])
+def test_advance_graph_replays_match_eager(S, n, ny, K):
+    b = I.basin(n, 2, ny=ny)
+    g = S.Grid(n, ny, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **F64)
+    q0 = [torch.empty(ny, n, **F64) for _ in range(3)]
+    S.swe_init(g, p, B, torch.tensor(b.eta0 * 20.0, **F64), q0)
+    spd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    S.swe_max_speed(g, p, B, q0, 0, spd)
+    dt0 = 1.2 * p.cfl_desired / float(spd.view(torch.float64).item())   # the first attempt is rejected
+    ea = [x.clone() for x in q0]
+    eb = [torch.empty_like(x) for x in q0]
+    ga = [x.clone() for x in q0]
+    gb = [torch.empty_like(x) for x in q0]
+    ctl_e, ctl_g = S.new_ctl(), S.new_ctl()
+    S.swe_ctl_set(ctl_e, 0.0, dt0, 1.0e30, 0)
+    S.swe_ctl_set(ctl_g, 0.0, dt0, 1.0e30, 0)
+    torch.cuda.synchronize()
+    check_replays(S, lambda: S.swe_advance(g, p, B, ea, eb, ctl_e, K),
+                  lambda st: S.swe_advance(g, p, B, ga, gb, ctl_g, K, stream=st),
+                  ctl_e, ctl_g, ea, eb, ga, gb)
+    assert S.read_ctl(ctl_g).s.n_rejected >= 1
+
+
+def test_level_graph_replays_match_eager(S):
+    ps = I.patches(200, seed=4)
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    B = torch.tensor(np.concatenate([x.ravel() for x in ps.B]), **F64)
+    eta = torch.tensor(np.concatenate([x.ravel() for x in ps.eta0]), **F64) * 20.0
+    p = S.Params()
+    q0 = [torch.empty(ncell, **F64) for _ in range(3)]
+    spd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for k in range(len(tab)):
+        o, m = tab[k].offset, tab[k].nx * tab[k].ny
+        gk = S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy)
+        qk = [x[o:o + m] for x in q0]
+        S.swe_init(gk, p, B[o:o + m], eta[o:o + m], qk)
+        S.swe_max_speed(gk, p, B[o:o + m], qk, 0, spd)
+    dt0 = p.cfl_desired / float(spd.view(torch.float64).item())
+    lv = S.Level(tab, S.SCHED_PACKED, chunk_rows=16)
+    ea = [x.clone() for x in q0]
+    eb = [torch.empty_like(x) for x in q0]
+    ga = [x.clone() for x in q0]
+    gb = [torch.empty_like(x) for x in q0]
+    ctl_e, ctl_g = S.new_ctl(), S.new_ctl()
+    S.swe_ctl_set(ctl_e, 0.0, dt0, 1.0e30, 0)
+    S.swe_ctl_set(ctl_g, 0.0, dt0, 1.0e30, 0)
+    torch.cuda.synchronize()
+    check_replays(S, lambda: S.level_advance(lv, p, B, ea, eb, ctl_e, 5),
+                  lambda st: S.level_advance(lv, p, B, ga, gb, ctl_g, 5, 0, stream=st),
+                  ctl_e, ctl_g, ea, eb, ga, gb)
