@@ -337,6 +337,14 @@ def busy_state(S, torch, I, np, f64, n):
 
 def secondary(S, torch, I, np, f64):
     out = {}
+    # measured device copy bandwidth (512 MiB read + 512 MiB written), the
+    # practical ceiling beside the published 8 TB/s
+    src = torch.ones(64 * 1024 * 1024, **f64)
+    dst = torch.empty_like(src)
+    t = min(_time_events(torch, lambda: dst.copy_(src), 10) for _ in range(3))
+    out["copy_512MiB_GBs"] = 2 * src.numel() * 8 / t / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
     # adjoint step at 1024^2 (linearized, f-wave, transverse)
     n = 1024
     b = I.basin(n, 3)
