@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--valu-from", metavar="SQ_DIR",
                     help="no GPU: read a rocprofv3 --pmc SQ_INSTS_VALU output of 'bench.py --busy-only 10' "
                          "and write profiles/step_nl_1024_valu.json")
+    ap.add_argument("--flag-only", type=int, default=0, metavar="K",
+                    help="run the 512^2 flag pass (34-snapshot window) K times and exit (profiler runs)")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
                     help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -187,6 +189,16 @@ def main():
     if args.serve_only:
         print(json.dumps({"serve": serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin,
                                                args.serve_nmax)}), flush=True)
+        return
+    if args.flag_only > 0:
+        flag, _, _ = flag_pass_512(S, torch, I, np, f64)
+        for _ in range(args.flag_only):
+            flag()
+        if args.copy_probe:
+            src = torch.ones(64 * 1024 * 1024, **f64)
+            torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"flag_launches": args.flag_only}), flush=True)
         return
     if args.busy_only > 0:
         g, p, B, qa, qb, dt = busy_state(S, torch, I, np, f64, args.n)
@@ -335,6 +347,30 @@ def busy_state(S, torch, I, np, f64, n):
     return g, p, B, qa, qb, dt
 
 
+FLAG_BYTES_PER_CELL_W34 = 32 + 24 * 34 + 1 + 1 + 1 + 16   # q, B, 34 snapshots, flag, accumulators
+
+
+def flag_pass_512(S, torch, I, np, f64):
+    """The flag pass at 512^2 with a 34-snapshot window (the widest window of
+    the adjoint-flagging workload: snapshots 30..63 of 64), with the running
+    flag and max-inner-product accumulators; returns the call and its
+    algorithmic bytes."""
+    n = 512
+    b = I.basin(n, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **f64)
+    K = 64
+    frames = torch.randn(K + 1, 3, n, n, **f64) * 1e-3
+    q = [torch.tensor(np.maximum(0.0, -b.B) + 0.0, **f64), torch.zeros(n, n, **f64), torch.zeros(n, n, **f64)]
+    fl = torch.empty(n, n, dtype=torch.int8, device=B.device)
+    acc = torch.zeros(n, n, dtype=torch.int8, device=B.device)
+    macc = torch.zeros(n, n, **f64)
+    ctx = dict(g=g, p=p, B=B, q=q, K=K, fl=fl, acc=acc, macc=macc)
+    return (lambda: S.adj_flag(g, p, B, q, frames, K, 30, 63, 1e-4, fl, None, acc, macc)), \
+        n * n * FLAG_BYTES_PER_CELL_W34, ctx
+
+
 def secondary(S, torch, I, np, f64):
     out = {}
     # measured device copy bandwidth (512 MiB read + 512 MiB written), the
@@ -357,21 +393,10 @@ def secondary(S, torch, I, np, f64):
     t = _time_events(torch, lambda: S.adj_step(g, p, B, q, r, 1.0), 200)
     out["adj_step_1024_cell_updates_per_s"] = n * n / t
     out["adj_step_1024_us"] = t * 1e6
-    # flagging pass at 512^2, 34-frame window (the widest window of the
-    # adjoint-flagging workload), all cells wet-checked
+    flag, fbytes, ctx = flag_pass_512(S, torch, I, np, f64)
+    t = _time_events(torch, flag, 100)
     n = 512
-    b = I.basin(n, 3)
-    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
-    B = torch.tensor(b.B, **f64)
-    K = 64
-    frames = torch.randn(K + 1, 3, n, n, **f64) * 1e-3
-    q = [torch.tensor(np.maximum(0.0, -b.B) + 0.0, **f64), torch.zeros(n, n, **f64), torch.zeros(n, n, **f64)]
-    fl = torch.empty(n, n, dtype=torch.int8, device=B.device)
-    acc = torch.zeros(n, n, dtype=torch.int8, device=B.device)
-    macc = torch.zeros(n, n, **f64)
-    t = _time_events(torch, lambda: S.adj_flag(g, p, B, q, frames, K, 30, 63, 1e-4, fl, None, acc, macc), 100)
-    W = 34
-    fbytes = n * n * (32 + 24 * W + 1 + 1 + 1 + 16)
+    g, p, B, q, K, fl, acc, macc = (ctx[k] for k in ("g", "p", "B", "q", "K", "fl", "acc", "macc"))
     out["flag_512_w34_us"] = t * 1e6
     out["flag_512_w34_GBs"] = fbytes / t / 1e9
     # the same pass with the snapshots on a 256^2 adjoint grid (bilinear
