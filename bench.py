@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--valu-from", metavar="SQ_DIR",
                     help="no GPU: read a rocprofv3 --pmc SQ_INSTS_VALU output of 'bench.py --busy-only 10' "
                          "and write profiles/step_nl_1024_valu.json")
+    ap.add_argument("--adj-only", type=int, default=0, metavar="K",
+                    help="run the 1024^2 adjoint step K times and exit (profiler runs)")
     ap.add_argument("--flag-only", type=int, default=0, metavar="K",
                     help="run the 512^2 flag pass (34-snapshot window) K times and exit (profiler runs)")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
@@ -189,6 +191,13 @@ def main():
     if args.serve_only:
         print(json.dumps({"serve": serve_bench(S, torch, I, np, args.serve_requests, args.serve_nmin,
                                                args.serve_nmax)}), flush=True)
+        return
+    if args.adj_only > 0:
+        step = adj_step_1024(S, torch, I, f64)
+        for _ in range(args.adj_only):
+            step()
+        torch.cuda.synchronize()
+        print(json.dumps({"adj_launches": args.adj_only}), flush=True)
         return
     if args.flag_only > 0:
         flag, _, _ = flag_pass_512(S, torch, I, np, f64)
@@ -371,6 +380,20 @@ def flag_pass_512(S, torch, I, np, f64):
         n * n * FLAG_BYTES_PER_CELL_W34, ctx
 
 
+def adj_step_1024(S, torch, I, f64):
+    """One adjoint step at 1024^2 (basin seed 3) from the Gaussian target of
+    radius 20 km, as a call."""
+    n = 1024
+    b = I.basin(n, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **f64)
+    q = [torch.zeros(n, n, **f64) for _ in range(3)]
+    r = [torch.empty(n, n, **f64) for _ in range(3)]
+    S.adj_target(g, p, B, b.target[0], b.target[1], 20e3, S.GAUSS, q)
+    return lambda: S.adj_step(g, p, B, q, r, 1.0)
+
+
 def secondary(S, torch, I, np, f64):
     out = {}
     # measured device copy bandwidth (512 MiB read + 512 MiB written), the
@@ -383,14 +406,7 @@ def secondary(S, torch, I, np, f64):
     torch.cuda.empty_cache()
     # adjoint step at 1024^2 (linearized, f-wave, transverse)
     n = 1024
-    b = I.basin(n, 3)
-    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
-    p = S.Params()
-    B = torch.tensor(b.B, **f64)
-    q = [torch.zeros(n, n, **f64) for _ in range(3)]
-    r = [torch.empty(n, n, **f64) for _ in range(3)]
-    S.adj_target(g, p, B, b.target[0], b.target[1], 20e3, S.GAUSS, q)
-    t = _time_events(torch, lambda: S.adj_step(g, p, B, q, r, 1.0), 200)
+    t = _time_events(torch, adj_step_1024(S, torch, I, f64), 200)
     out["adj_step_1024_cell_updates_per_s"] = n * n / t
     out["adj_step_1024_us"] = t * 1e6
     flag, fbytes, ctx = flag_pass_512(S, torch, I, np, f64)
