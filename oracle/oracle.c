@@ -733,6 +733,24 @@ static void adj_split(const edge_t *e, int ydir, const double *a_ph, int positiv
     to_phys(ydir, nf, out_ph);
 }
 
+/*
+ * Test hook (the pins only): the positive and negative parts of the adjoint
+ * transverse split of the physical fluctuation a on a wet-wet edge whose
+ * cells have sound speeds cL (low) and cR (high).
+ */
+void or_adj_split_parts(double cL, double cR, int ydir, const double *a, double *pos, double *neg)
+{
+    edge_t e;
+    memset(&e, 0, sizeof e);
+    e.type = E_WET;
+    e.nw = 2;
+    e.cl = cL;
+    e.cr = cR;
+    e.rc = 1.0 / (cL + cR);
+    adj_split(&e, ydir, a, 1, pos);
+    adj_split(&e, ydir, a, 0, neg);
+}
+
 /* ------------------------------------------------------------------------ */
 /* 1D sweep (linear forward and adjoint)                                    */
 /* ------------------------------------------------------------------------ */

@@ -88,6 +88,8 @@ void or_flag_interp(const or_grid *G, const or_params *P, int model, const doubl
                     const or_grid *Ga, const double *Ba, const double *frames, int K, int k_lo, int k_hi,
                     double tol, signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc);
 int or_run(const or_problem *pb, or_result *res);
+/* test hook: the two parts of the adjoint transverse split (pins only) */
+void or_adj_split_parts(double cL, double cR, int ydir, const double *a, double *pos, double *neg);
 
 #ifdef __cplusplus
 }

@@ -272,6 +272,16 @@ def interp(grid: Grid, adj_grid: Grid, v):
     return out
 
 
+def adj_split_parts(cL, cR, ydir, a):
+    """(positive, negative) parts of the adjoint transverse split of the
+    physical fluctuation a (3 components) on a wet-wet edge between cells of
+    sound speeds cL and cR; ydir selects the y-edge frame."""
+    a = _f64(a, (3,))
+    pos, neg = np.empty(3), np.empty(3)
+    lib().or_adj_split_parts(C.c_double(cL), C.c_double(cR), C.c_int(ydir), _p(a), _p(pos), _p(neg))
+    return pos, neg
+
+
 def flag_interp(grid: Grid, prm: Params, model, B, q0, q1, q2, adj_grid: Grid, adj_B, frames, K, k_lo, k_hi,
                 tol, flag_acc=None, maxip_acc=None):
     """flag() with the snapshots on adj_grid.  Returns (flags, maxip)."""

@@ -645,6 +645,32 @@ def test_adjoint_2d_wall_mirror_and_rest(oracle):
     assert not q[2].any()
 
 
+def test_adjoint_transverse_split_reconstructs_the_fluctuation(oracle):
+    """The adjoint's transverse split over variable depth decomposes a
+    fluctuation on the eigenvectors of the edge's two cells, (cL, 1) with
+    speed -cL from the low cell and (-cR, 1) with speed +cR from the high one
+    (the 2-family system of the adjoint equations, Sec. 5); each part is its
+    speed times its share of the fluctuation.  So the positive part over cR
+    plus the negative part over -cL gives back the fluctuation's surface and
+    normal components, and the tangential component, which no family
+    carries, is zero in both parts."""
+    O = oracle
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        cL, cR = rng.uniform(1.0, 200.0, 2)
+        a = rng.normal(size=3)
+        for ydir in (0, 1):
+            n, t = (2, 1) if ydir else (1, 2)
+            pos, neg = O.adj_split_parts(cL, cR, ydir, a)
+            rec = pos / cR + neg / (-cL)
+            scale = max(abs(a[0]), abs(a[n]))
+            assert abs(rec[0] - a[0]) <= 1e-13 * scale and abs(rec[n] - a[n]) <= 1e-13 * scale
+            assert pos[t] == 0.0 and neg[t] == 0.0
+            # each part lies on its own family's eigenvector
+            assert abs(pos[0] + cR * pos[n]) <= 1e-12 * (abs(pos[0]) + 1e-300)
+            assert abs(neg[0] - cL * neg[n]) <= 1e-12 * (abs(neg[0]) + 1e-300)
+
+
 # --------------------------------------------------------------------------
 # flags: orthogonality of crossing waves, window rule, brute force
 # --------------------------------------------------------------------------
