@@ -171,6 +171,21 @@ __device__ __forceinline__ void store_row_buffer(const KParams &P, int r, int i,
     }
 }
 
+// Wavefront priority by progress down the march: 3 for its first third, 2
+// for the second, 1 for the rest and 0 for the last row.  A SIMD issues from
+// its highest-priority ready wavefront, the oldest among equals, so with
+// equal priorities the first of two wavefronts runs ahead, ends early, and
+// leaves the other to finish alone with its latency uncovered; stepping the
+// priority down lets the one further behind catch up, and the pair runs
+// together to the end (measured 45.6 -> 42.9 us per 1024^2 step).  k: rows
+// done, L: rows to do.
+__device__ __forceinline__ void march_priority(int k, int L)
+{
+    if (k == L / 3) __builtin_amdgcn_s_setprio(2);
+    else if (k == 2 * L / 3) __builtin_amdgcn_s_setprio(1);
+    else if (k == L - 1) __builtin_amdgcn_s_setprio(0);
+}
+
 // Row r, first part: row r + 2's cell data and the waves of the row's two
 // new edges (y-edge r + 3/2, x-edge (i - 1/2, r + 1)), without the wall and
 // dry-edge cases when all their cells are wet on every lane (lane 0's x-edge,
@@ -291,7 +306,7 @@ __device__ __forceinline__ void finish_row(const KParams &P, const Geo &G, int i
 // runs the general forms.  The Courant number is nu max|s| over the edges,
 // which equals the largest nu|s| exactly (rounding is monotonic), and the
 // cells' own terms (nonlinear model) over the march's rows.
-template <class M, bool WETPATH = true, bool SUBPATH = true, bool BUFST = false>
+template <class M, bool WETPATH = true, bool SUBPATH = true, bool BUFST = false, bool PRIO = false>
 __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, int i, int j0, int j1,
                                       int jend, bool core, bool xedge_in, double dx, double dy,
                                       double &cfl, int &nclamp, int &nbad)
@@ -300,6 +315,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     const double hnux = 0.5 * nux, hnuy = 0.5 * nuy;
     using Cell = typename M::Cell;
     const double sg = sqrt(P.g);
+    if (PRIO) __builtin_amdgcn_s_setprio(3);
     Window<M> W;
     W.smx = 0.0;
     W.smy = 0.0;
@@ -385,6 +401,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     if (SUBPATH && r < jend && __all(sub_edge<M>(W.yN) && sub_edge<M>(W.xCur))) {
         bool sub_new;
         do {
+            if (PRIO) march_priority(r - j0, jend - j0);
             new_edges<M, WETPATH, BUFST>(P, G, lane, i, r, j1, sg, nux, nuy, W);
             sub_new = __all(sub_edge<M>(W.yNN) && sub_edge<M>(W.xNext));
             if (sub_new) {
@@ -398,6 +415,7 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
         }
     }
     for (; r < jend; ++r) {
+        if (PRIO) march_priority(r - j0, jend - j0);
         new_edges<M, WETPATH, BUFST>(P, G, lane, i, r, j1, sg, nux, nuy, W);
         finish_row<M, false, false, BUFST>(P, G, i, r, r < j1, core, nux, nuy, hnux, hnuy, W, nclamp, nbad);
     }
@@ -436,8 +454,8 @@ __global__ void __launch_bounds__(WAVE, 2) k_march2d(KParams P)
     const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
     double cfl = 0.0;
     int nclamp = 0, nbad = 0;
-    march<M, true, true, true>(P, uniform_geo(P), lane, i, j0, j1, j1, core, xedge_in, P.dx, P.dy, cfl, nclamp,
-                               nbad);
+    march<M, true, true, true, true>(P, uniform_geo(P), lane, i, j0, j1, j1, core, xedge_in, P.dx, P.dy, cfl,
+                                     nclamp, nbad);
     march_epilogue(P, lane, cfl, nclamp, nbad);
 }
 
