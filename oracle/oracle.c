@@ -42,6 +42,9 @@
 #include <string.h>
 
 #include "oracle.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define MAXD(a, b) ((a) > (b) ? (a) : (b))
 #define MIND(a, b) ((a) < (b) ? (a) : (b))
@@ -1366,12 +1369,13 @@ int or_run(const or_problem *pb, or_result *res)
 #define DO_FLAG(store_idx) do { \
         int ok = or_window(t, pb->t0, pb->ts, pb->tf, K, &klo, &khi); \
         if (!ok) { klo = 1; khi = 0; } \
+        double *m_out = ((store_idx) >= 0 && pb->maxip_at) ? pb->maxip_at + (size_t)(store_idx) * n : NULL; \
         if (interp) \
             or_flag_interp(G, P, pb->model, pb->B, a[0], a[1], a[2], GA, BA, pb->frames, K, klo, khi, \
-                           pb->tol, fl, NULL, pb->flag_acc, pb->maxip_acc); \
+                           pb->tol, fl, m_out, pb->flag_acc, pb->maxip_acc); \
         else \
             or_flag(G, P, pb->model, pb->B, a[0], a[1], a[2], pb->frames, K, klo, khi, pb->tol, \
-                    fl, NULL, pb->flag_acc, pb->maxip_acc); \
+                    fl, m_out, pb->flag_acc, pb->maxip_acc); \
         if ((store_idx) >= 0 && pb->flags_at) memcpy(pb->flags_at + (size_t)(store_idx) * n, fl, n); \
         if ((store_idx) >= 0 && pb->surface_flags_at) \
             or_surface_flag(G, P, pb->model, pb->B, a[0], pb->surface_tol, \
@@ -1419,4 +1423,15 @@ done:
     free(fl);
     for (int c = 0; c < 3; c++) { free(a[c]); free(b[c]); }
     return res->status;
+}
+
+/* Threads of the row loops from now on (tiny grids run fastest on one);
+ * a no-op without OpenMP.  Results never depend on it. */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }

@@ -47,6 +47,8 @@ typedef struct {
     signed char *surface_flags_at;  /* (K+1) * nx * ny surface flags at t0 and the output times, nullable */
     or_grid adj_grid;               /* nx == 0: the adjoint runs on the forward grid; else on this one */
     const double *adj_B;            /* bottom on adj_grid */
+    double *maxip_at;               /* (K+1) * nx * ny: the max inner product m of the flag pass at t0 and
+                                       at each output time (the values flags_at thresholds), nullable */
 } or_problem;
 
 typedef struct {
@@ -88,6 +90,8 @@ void or_flag_interp(const or_grid *G, const or_params *P, int model, const doubl
                     const or_grid *Ga, const double *Ba, const double *frames, int K, int k_lo, int k_hi,
                     double tol, signed char *flags, double *maxip, signed char *flag_acc, double *maxip_acc);
 int or_run(const or_problem *pb, or_result *res);
+/* threads of the row loops (results do not depend on it) */
+void or_set_threads(int n);
 /* test hook: the two parts of the adjoint transverse split (pins only) */
 void or_adj_split_parts(double cL, double cR, int ydir, const double *a, double *pos, double *neg);
 

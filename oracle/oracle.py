@@ -59,7 +59,7 @@ class _Problem(C.Structure):
                 ("frames", _dp), ("q_out", _dp * 3),
                 ("flags_at", _bp), ("flag_acc", _bp), ("maxip_acc", _dp),
                 ("surface_tol", C.c_double), ("surface_flags_at", _bp),
-                ("adj_grid", _Grid), ("adj_B", _dp)]
+                ("adj_grid", _Grid), ("adj_B", _dp), ("maxip_at", _dp)]
 
 
 class _Result(C.Structure):
@@ -221,6 +221,11 @@ def adj_nsub(grid: Grid, prm: Params, B, t0, tf, K):
     return ns, dt.value
 
 
+def set_threads(n: int):
+    """Threads of the oracle's row loops (results do not depend on it)."""
+    lib().or_set_threads(C.c_int(int(n)))
+
+
 def window(t, t0, ts, tf, K):
     """Returns (k_lo, k_hi) or None when t > tf."""
     lo, hi = C.c_int(0), C.c_int(0)
@@ -261,6 +266,7 @@ class RunResult:
     dt_adj: float
     t_end: float
     surface_flags_at: np.ndarray = None
+    maxip_at: np.ndarray = None      # max inner product of the flag pass at t0 and each output time
     extra: dict = field(default_factory=dict)
 
 
@@ -321,6 +327,7 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
     frames = np.zeros((K + 1, ncomp) + ashp)
     q = [np.zeros(shp) for _ in range(3)]
     flags_at = np.zeros((K + 1,) + shp, np.int8)
+    maxip_at = np.zeros((K + 1,) + shp)
     acc = np.zeros(shp, np.int8)
     macc = np.zeros(shp)
     pb = _Problem()
@@ -336,6 +343,7 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
     for c in range(3):
         pb.q_out[c] = _p(q[c])
     pb.flags_at, pb.flag_acc, pb.maxip_acc = _b(flags_at), _b(acc), _p(macc)
+    pb.maxip_at = _p(maxip_at)
     sflags = None
     if surface_tol is not None:
         sflags = np.zeros((K + 1,) + shp, np.int8)
@@ -350,4 +358,4 @@ def run(grid: Grid, prm: Params, model, B, eta0, target_xyR, t0, ts, tf, K, tol,
                      n_adj_steps=res.n_adj_steps, n_sub=res.n_sub, n_fwd_steps=res.n_fwd_steps,
                      n_rejected=res.n_rejected, n_flag_calls=res.n_flag_calls,
                      n_clamped=res.n_clamped, status=res.status, dt_adj=res.dt_adj,
-                     t_end=res.t_end, surface_flags_at=sflags)
+                     t_end=res.t_end, surface_flags_at=sflags, maxip_at=maxip_at)

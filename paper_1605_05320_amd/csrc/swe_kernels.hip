@@ -425,14 +425,19 @@ __device__ __forceinline__ void march(const KParams &P, const Geo &G, int lane, 
     cfl = fmax_(cfl, fmax_(fmax_(cx, cy), cc));
 }
 
-// Wavefront epilogue: Courant number and counters of the launch.
+// Wavefront epilogue: Courant number and counters of the launch (clamped
+// and non-finite cells, summed over the wavefront's lanes).
 __device__ __forceinline__ void march_epilogue(const KParams &P, int lane, double cfl, int nclamp, int nbad)
 {
     cfl = wave_max(cfl);
-    unsigned long long mc = __ballot(nclamp > 0), mb = __ballot(nbad > 0);
+    int sc = 0, sb = 0;
+    if (__any(nclamp > 0 || nbad > 0)) {
+        sc = wave_sum(nclamp);
+        sb = wave_sum(nbad);
+    }
     if (lane == 0) {
-        if (mc && P.n_clamped) atomicAdd(P.n_clamped, __popcll(mc));
-        if (mb && P.n_nonfinite) atomicAdd(P.n_nonfinite, __popcll(mb));
+        if (sc && P.n_clamped) atomicAdd(P.n_clamped, sc);
+        if (sb && P.n_nonfinite) atomicAdd(P.n_nonfinite, sb);
         if (P.cfl_bits)
             atomicMax(P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0),
                       (unsigned long long)__double_as_longlong(cfl));

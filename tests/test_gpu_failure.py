@@ -1,0 +1,175 @@
+"""Failure detection and resumption through the C ABI: non-finite states are
+counted and end a run with SWE_E_NONFINITE; clamped negative depths are
+counted cell by cell as the oracle counts them; a device-controlled run
+stopped after n attempts, copied (state and control block) and resumed gives
+the same bits as the uninterrupted run.  Every condition is a data value:
+every kernel runs to its end."""
+import numpy as np
+import pytest
+
+from paper_1605_05320_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_05320_amd import swe
+    swe.lib()
+    return swe
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def shoreline_layer(seed=3, nx=70, ny=24):
+    """Deep-ish water (2 m) west, a thin layer (2..20 mm) draining westward
+    from a dry beach east of column 40: large steps drive some of its cells
+    below zero."""
+    rng = np.random.default_rng(seed)
+    B = np.full((ny, nx), -2.0)
+    B[:, 40:] = 1.0
+    h = np.maximum(0.0, -B)
+    h[:, 30:40] = rng.uniform(0.002, 0.02, (ny, 10))
+    B[:, 30:40] = -h[:, 30:40]
+    hu = np.zeros_like(h)
+    hv = np.zeros_like(h)
+    hu[:, 30:40] = -h[:, 30:40] * rng.uniform(0.5, 3.0, (ny, 10))
+    hv[:, 30:40] = h[:, 30:40] * rng.uniform(-1.0, 1.0, (ny, 10))
+    return B, [h, hu, hv]
+
+
+@pytest.mark.parametrize("dt", [3.0, 4.0])
+def test_clamped_cells_counted_like_the_oracle(oracle, S, dt):
+    O = oracle
+    B, q = shoreline_layer()
+    ny, nx = B.shape
+    print(f"clamp count: {nx}x{ny} shoreline layer, dt = {dt}", flush=True)
+    h, hu, hv, cfl, ncl = O.swe_step(O.Grid(nx, ny, 10.0, 10.0), O.Params(), B, *q, dt)
+    assert ncl > 0
+    a = [dev(x) for x in q]
+    b = [torch.empty_like(x) for x in a]
+    sc = torch.zeros(2, dtype=torch.int64, device=DEV)
+    S.swe_step(S.Grid(nx, ny, 10.0, 10.0), S.Params(), dev(B), a, b, dt, sc)
+    torch.cuda.synchronize()
+    words = host(sc)
+    n_clamped = int(words[1] & 0xffffffff)
+    n_nonfinite = int(words[1] >> 32)
+    assert n_clamped == ncl and n_nonfinite == 0
+    assert np.array_equal(host(b[0]), h) and np.array_equal(host(b[1]), hu) and np.array_equal(host(b[2]), hv)
+    assert float(sc[0:1].view(torch.float64).item()) == cfl
+    print(f"clamp count: {n_clamped} cells, as the oracle")
+
+
+def test_nonfinite_cells_counted(oracle, S):
+    """Two cells of a basin state hold NaN momentum: the step counts the
+    output cells with a non-finite value, as many as the oracle's output
+    has."""
+    O = oracle
+    n = 96
+    b = I.basin(n, 3)
+    go = O.Grid(n, n, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    q = O.init_state(go, p, O.NONLINEAR, b.B, b.eta0)
+    q[1][40, 20] = np.nan
+    q[2][70, 33] = np.nan
+    dt = 0.5 * O.dt0(go, p, O.NONLINEAR, b.B, q[0], np.zeros_like(q[0]), np.zeros_like(q[0]))
+    print("non-finite count: 96^2 basin with two NaN momenta", flush=True)
+    out = O.swe_step(go, p, b.B, *q, dt)
+    bad = int((~(np.isfinite(out[0]) & np.isfinite(out[1]) & np.isfinite(out[2]))).sum())
+    assert bad >= 2
+    a = [dev(x) for x in q]
+    bb = [torch.empty_like(x) for x in a]
+    sc = torch.zeros(2, dtype=torch.int64, device=DEV)
+    S.swe_step(S.Grid(n, n, b.grid.dx, b.grid.dy), S.Params(), dev(b.B), a, bb, dt, sc)
+    torch.cuda.synchronize()
+    assert int(host(sc)[1] >> 32) == bad
+
+
+def test_run_with_nonfinite_source_fails_cleanly(S):
+    """A NaN in the initial surface of a wet cell makes the driver stop with
+    SWE_E_NONFINITE (a status, not a fault), and the library keeps working."""
+    n = 64
+    b = I.basin(n, 3)
+    eta0 = b.eta0.copy()
+    eta0[30, 20] = np.nan
+    gs = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    K = 4
+    frames = torch.zeros(K + 1, 3, n, n, dtype=torch.float64, device=DEV)
+    q_out = [torch.zeros(n, n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    acc = torch.zeros(n, n, dtype=torch.int8, device=DEV)
+    print("driver with a NaN source cell", flush=True)
+    pb = S.make_problem(gs, S.Params(), dev(b.B), dev(eta0), (b.target[0], b.target[1], 60e3), 0.0, 900.0,
+                        1800.0, K, 1e-4, frames, q_out, None, acc, None)
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, dtype=torch.float64, device=DEV)
+    with pytest.raises(S.SweError) as ei:
+        S.swe_run(pb, ws)
+    assert ei.value.status == S.E_NONFINITE
+    # the same problem without the NaN runs
+    pb2 = S.make_problem(gs, S.Params(), dev(b.B), dev(b.eta0), (b.target[0], b.target[1], 60e3), 0.0, 900.0,
+                         1800.0, K, 1e-4, frames, q_out, None, acc, None)
+    res = S.swe_run(pb2, ws)
+    assert res.n_fwd_steps > 0
+
+
+def test_stop_copy_resume_is_bit_identical(S):
+    """A device-controlled run of 80 attempts toward an output time, against
+    the same run stopped after 30 attempts, its two state plane sets and its
+    control block copied to fresh buffers, and resumed there for 50 more:
+    same state, time, next step, counts and current plane set, bit for bit.
+    Then both are retargeted to a later output time and advanced again."""
+    n = 200
+    b = I.basin(n, 12)
+    grid = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    prm = S.Params(cfl_desired=0.9, cfl_max=0.95)
+    B = dev(b.B)
+    a = [torch.empty(n, n, dtype=torch.float64, device=DEV) for _ in range(3)]
+    S.swe_init(grid, prm, B, dev(b.eta0 * 30.0), a)
+    spd = torch.zeros(1, dtype=torch.int64, device=DEV)
+    S.swe_max_speed(grid, prm, B, a, 0, spd)
+    dt0 = prm.cfl_desired / float(spd.view(torch.float64).item())
+    t_out = 70.5 * dt0
+    print("stop / copy / resume: 200^2 basin", flush=True)
+
+    def fresh():
+        qa = [x.clone() for x in a]
+        qb = [torch.full_like(x, float("nan")) for x in a]
+        ctl = S.new_ctl()
+        S.swe_ctl_set(ctl, 0.0, 1.3 * dt0, t_out, 0)
+        return qa, qb, ctl
+
+    ra, rb, rctl = fresh()
+    S.swe_advance(grid, prm, B, ra, rb, rctl, 80)
+    sa, sb, sctl = fresh()
+    S.swe_advance(grid, prm, B, sa, sb, sctl, 30)
+    torch.cuda.synchronize()
+    ca, cb, cctl = [x.clone() for x in sa], [x.clone() for x in sb], sctl.clone()
+    del sa, sb, sctl
+    S.swe_advance(grid, prm, B, ca, cb, cctl, 50)
+    torch.cuda.synchronize()
+    r, c = S.read_ctl(rctl), S.read_ctl(cctl)
+    assert r.n_rejected >= 1 and r.done == 1
+    for f in ("t", "dt", "cur", "done", "n_accepted", "n_rejected", "final_step"):
+        assert getattr(r, f) == getattr(c, f), f
+    rq, cq = (ra if r.cur == 0 else rb), (ca if c.cur == 0 else cb)
+    assert all(torch.equal(x, y) for x, y in zip(rq, cq))
+    # both retargeted to a later time and advanced again
+    for ctl, qa, qb in ((rctl, ra, rb), (cctl, ca, cb)):
+        S.swe_ctl_retarget(ctl, t_out + 20.25 * dt0)
+        S.swe_advance(grid, prm, B, qa, qb, ctl, 30)
+    torch.cuda.synchronize()
+    r, c = S.read_ctl(rctl), S.read_ctl(cctl)
+    assert r.done == 1 and (r.t, r.dt, r.n_accepted, r.cur) == (c.t, c.dt, c.n_accepted, c.cur)
+    rq, cq = (ra if r.cur == 0 else rb), (ca if c.cur == 0 else cb)
+    assert all(torch.equal(x, y) for x, y in zip(rq, cq))
+    print(f"resume: {r.n_accepted} accepted, {r.n_rejected} rejected, identical")

@@ -428,7 +428,8 @@ def _run_pair(O, S, go, gs, model, B, eta0, target, t0, ts, tf, K, tol, flag_eve
 
 
 def _flags_match(fg, fc, maxip_c, tol):
-    """Flags equal except where the oracle's max inner product is within 1e-12 of tol."""
+    """Flags equal except where the oracle's max inner product (of the same
+    flag pass) is within 1e-12 of tol."""
     band = np.abs(maxip_c - tol) <= 1e-12 * tol
     return np.array_equal(fg[~band], fc[~band])
 
@@ -497,7 +498,7 @@ def test_run_2d_coarse_adjoint_parity(oracle, S):
     assert close(host(macc), rc.maxip_acc)
     assert _flags_match(host(acc), rc.flag_acc, rc.maxip_acc, tol)
     for j in range(K + 1):
-        assert _flags_match(host(flags_at)[j], rc.flags_at[j], rc.maxip_acc, tol)
+        assert _flags_match(host(flags_at)[j], rc.flags_at[j], rc.maxip_at[j], tol)
     assert rc.flag_acc.any()
 
 
@@ -519,7 +520,7 @@ def test_run_2d_parity(oracle, S, flag_every, ts):
     assert close(macc, rc.maxip_acc)
     assert _flags_match(acc, rc.flag_acc, rc.maxip_acc, 1e-4)
     for j in range(17):
-        assert np.array_equal(flags_at[j], rc.flags_at[j]) or _flags_match(flags_at[j], rc.flags_at[j], rc.maxip_acc, 1e-4)
+        assert _flags_match(flags_at[j], rc.flags_at[j], rc.maxip_at[j], 1e-4)
     assert rc.flag_acc.any()
 
 

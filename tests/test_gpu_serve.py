@@ -61,7 +61,14 @@ def test_mix_equals_alone(S):
     arena = arena_for(S, reqs, copies=4)
     _, st = S.serve(reqs, arena, 4)
     slots = {s["slot"] for s in st}
-    assert len(slots) > 1, "the mix never ran two scenarios at once"
+    assert len(slots) > 1, "the mix never used two slots"
+    # at least two requests were in flight together: their admitted..finished
+    # intervals overlap (the mix really ran side by side)
+    spans = sorted((s["admitted"], s["finished"]) for s in st)
+    overlaps = sum(1 for k in range(len(spans)) for m in range(k + 1, len(spans))
+                   if spans[m][0] < spans[k][1] and spans[k][0] < spans[m][1])
+    print(f"mix: {len(slots)} slots, {overlaps} overlapping pairs of requests")
+    assert overlaps >= 1, "no two requests were in flight at the same time"
     for r, s, (ref, s1) in zip(reqs, st, alone):
         assert s["status"] == 0
         assert s["n_fwd_steps"] == s1["n_fwd_steps"] and s["n_adj_steps"] == s1["n_adj_steps"]
