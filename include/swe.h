@@ -579,6 +579,23 @@ SWE_API size_t swe_run_workspace_bytes(const swe_problem *pb);
 SWE_API swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_bytes,
                    swe_result *res, void *stream);
 
+/*
+ * swe_run_static - swe_run for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same driver, whose workspace is instead a fixed array of
+ * SWE_STATIC_WORKSPACE_BYTES in the library's device memory (one per GPU,
+ * held from the first call on that GPU until the process ends).  It calls no
+ * allocating routine; the caller still provides every input and output of
+ * the problem.  A problem whose swe_run_workspace_bytes exceed the array
+ * (grids beyond about 1170^2 cells with pitch = nx) is refused with
+ * SWE_E_NOMEM before anything is enqueued.  All calls on one GPU share its
+ * array: calls that overlap in time on the same GPU (other host threads,
+ * other streams) race and must be serialised by the caller.  Otherwise as
+ * swe_run (synchronises `stream`, same results bit for bit).
+ */
+#define SWE_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+SWE_API swe_status swe_run_static(const swe_problem *pb, swe_result *res, void *stream);
+
 /* Message for the last non-OK status returned on this thread ("" if none). */
 SWE_API const char *swe_last_error(void);
 

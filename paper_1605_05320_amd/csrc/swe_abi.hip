@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -707,6 +708,48 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     HIP_TRY(hipStreamSynchronize(s));
     res->t_end = t;
     return SWE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free driver: the workspace is a fixed array in the library's
+// device memory (every GPU the library runs on holds its own copy)
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SWE_STATIC_WORKSPACE_BYTES];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current.  In host code `scratch` only names the symbol;
+// its device address must come from the runtime.
+static swe_status scratch_address(void **out)
+{
+    static std::mutex mu;
+    static void *addr[64] = {};
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(SWE_E_HIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SWE_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return SWE_OK;
+}
+
+swe_status swe_run_static(const swe_problem *pb, swe_result *res, void *stream)
+{
+    swe_status st;
+    if ((st = check_problem(pb)) != SWE_OK) return st;
+    if (!res) return fail(SWE_E_INVAL, "result is NULL");
+    const size_t need = ws_layout(pb, nullptr, nullptr);
+    if (need > SWE_STATIC_WORKSPACE_BYTES)
+        return fail(SWE_E_NOMEM, "problem needs %zu bytes of workspace, the static workspace holds %zu "
+                    "(use swe_run with a workspace of the caller's)", need, (size_t)SWE_STATIC_WORKSPACE_BYTES);
+    void *ws = nullptr;
+    if ((st = scratch_address(&ws)) != SWE_OK) return st;
+    return swe_run(pb, ws, SWE_STATIC_WORKSPACE_BYTES, res, stream);
 }
 
 } // extern "C"

@@ -112,7 +112,8 @@ def lib():
         for name in ("swe_step", "adj_step", "adj_target", "swe_init", "swe_max_speed", "adj_window",
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
                      "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
-                     "swe_serve", "swe_surface_flag", "adj_flag_interp", "swe_cluster", "swe_prolong"):
+                     "swe_serve", "swe_surface_flag", "adj_flag_interp", "swe_cluster", "swe_prolong",
+                     "swe_run_static"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_serve_footprint.restype = C.c_size_t
@@ -266,6 +267,16 @@ def swe_run(pb: swe_problem, workspace, stream=None) -> swe_result:
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().swe_run(C.byref(pb), _ptr(workspace), C.c_size_t(nbytes), C.byref(res),
                          _stream(stream)))
+    return res
+
+
+STATIC_WORKSPACE_BYTES = 64 << 20     # SWE_STATIC_WORKSPACE_BYTES
+
+
+def swe_run_static(pb: swe_problem, stream=None) -> swe_result:
+    """swe_run with the library's own fixed device workspace (no allocation)."""
+    res = swe_result()
+    _check(lib().swe_run_static(C.byref(pb), C.byref(res), _stream(stream)))
     return res
 
 

@@ -159,3 +159,23 @@ def test_step_rejects_parameters_out_of_range_before_touching_the_device(S, fiel
         S.swe_step(g, prm, B, qa, qb, 0.1, stream=null_stream)
     assert e.value.status == S.E_INVAL
     assert "1e-100" in S.lib().swe_last_error().decode()
+
+
+def test_static_driver_refuses_a_problem_beyond_its_array(S):
+    """swe_run_static refuses a grid whose workspace exceeds its fixed array
+    before any device work (the pointers are never touched)."""
+    n = 1200
+    g = S.Grid(n, n, 1000.0, 1000.0)
+    fake = C.c_void_p(0x1000)
+
+    class T:            # a stand-in device pointer (never dereferenced)
+        def data_ptr(self):
+            return fake.value
+    t = T()
+    pb = S.make_problem(g, S.Params(), t, t, (0.0, 0.0, 1e4), 0.0, 0.0, 1.0, 1, 1e-4, t, [t, t, t])
+    assert S.swe_run_workspace_bytes(pb) > S.STATIC_WORKSPACE_BYTES
+    null_stream = type("Stream", (), {"cuda_stream": 0})()
+    with pytest.raises(S.SweError) as ei:
+        S.swe_run_static(pb, stream=null_stream)
+    assert ei.value.status == S.E_NOMEM
+    assert "static workspace" in str(ei.value)
