@@ -181,12 +181,26 @@ SWE_API swe_status adj_window(double t, double t0, double ts, double tf, int32_t
  * the grid's pitch, snapshot k plane c at frames + (k*ncomp + c)*ny*pitch.
  * An empty window (k_lo > k_hi) gives m = 0.  flags (int8 plane) and the
  * optional maxip, flag_acc (|= flag), maxip_acc (= max(., m)) planes use the
- * grid's pitch.
+ * grid's pitch.  bounds (device, nullable): the snapshots' non-zero boxes of
+ * adj_frame_bounds; a snapshot whose box excludes a cell is not read for that
+ * cell (its inner product there is |0| = 0: the same m, less traffic).
  */
 SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B,
                     swe_fields q, const double *frames, int32_t K, int32_t k_lo,
                     int32_t k_hi, double tol, int8_t *flags, double *maxip,
-                    int8_t *flag_acc, double *maxip_acc, void *stream);
+                    int8_t *flag_acc, double *maxip_acc, const int32_t *bounds, void *stream);
+
+/*
+ * adj_frame_bounds - for each snapshot k = 0..K of `frames` (laid out as for
+ * adj_flag on `grid`), the smallest box holding every cell with a non-zero
+ * value in any plane (a NaN counts as non-zero): bounds[4k..4k+3] =
+ * (i_lo, i_hi, j_lo, j_hi), inclusive; (nx, -1, ny, -1) for a snapshot that is
+ * zero everywhere.  The adjoint is exactly zero outside the domain of
+ * dependence of the target (Sec. 4), so early snapshots have small boxes.
+ * bounds: device, 4*(K+1) int32.  Enqueue only.
+ */
+SWE_API swe_status adj_frame_bounds(const swe_grid *grid, const double *frames, int32_t K, int32_t *bounds,
+                                    void *stream);
 
 /*
  * Device-side time-step control (the CFL rule of swe_run, phase B), so that a
@@ -220,7 +234,7 @@ typedef struct {
 typedef struct {
     swe_ctl_state s;        /* state after the last attempt (valid between swe_advance calls) */
     uint64_t cfl_bits;      /* Courant number of the last attempt */
-    int32_t n_clamped, n_nonfinite;
+    int32_t n_clamped, n_nonfinite;   /* cells clamped / non-finite in accepted attempts */
     int32_t n_flag_calls;   /* flag passes run by swe_advance_flagged */
     int32_t reserved;
     swe_ctl_state slot[2];  /* kernel-internal: state of the running attempts */
@@ -229,7 +243,9 @@ typedef struct {
      * being the largest of ring[k][j][0] over j < SWE_CTL_SPREAD: the
      * wavefronts of a launch spread their atomic maxima over these words, one
      * 128-byte line each (atomics on one word are serialised, which made a
-     * single word cost microseconds per launch) */
+     * single word cost microseconds per launch); words 1 and 2 of each line
+     * collect the attempt's clamped and non-finite cells, which are added to
+     * n_clamped and n_nonfinite once the attempt is known to be accepted */
     uint64_t ring[3][SWE_CTL_SPREAD][16];
 } swe_ctl;
 
@@ -378,13 +394,16 @@ SWE_API swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm,
  * w = clamp(u - 1/2 - i0, 0, 1) (constant beyond the outermost centres);
  * q^ = (1-wy)((1-wx) q00 + wx q10) + wy((1-wx) q01 + wx q11).  The cell is
  * adjoint-wet iff max(0, sea_level - adj_B) > dry_tol in its adjoint cell.
- * frames: (K+1) * ncomp planes with adj_grid's pitch.  Other arguments and
- * errors as adj_flag.  Enqueue only.
+ * frames: (K+1) * ncomp planes with adj_grid's pitch; bounds (nullable) are
+ * boxes on adj_grid, and a snapshot is skipped for a cell when none of its
+ * four interpolation corners lies in the box.  Other arguments and errors as
+ * adj_flag.  Enqueue only.
  */
 SWE_API swe_status adj_flag_interp(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
                                    const swe_grid *adj_grid, const double *adj_B, const double *frames,
                                    int32_t K, int32_t k_lo, int32_t k_hi, double tol, int8_t *flags,
-                                   double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream);
+                                   double *maxip, int8_t *flag_acc, double *maxip_acc, const int32_t *bounds,
+                                   void *stream);
 
 /* Flagging of a device-controlled forward run (see swe_advance_flagged). */
 typedef struct {
@@ -397,6 +416,7 @@ typedef struct {
     double *maxip_acc;      /* max of all m (nullable) */
     const swe_grid *adj_grid;  /* snapshots on a grid of their own (as adj_flag_interp); NULL: the forward grid */
     const double *adj_B;       /* bottom on adj_grid (with adj_grid) */
+    const int32_t *bounds;     /* non-zero boxes of the snapshots (adj_frame_bounds), nullable */
 } swe_flagging;
 
 /*
@@ -534,7 +554,8 @@ typedef struct {
     double t0, ts, tf;      /* run [t0, tf]; target time range [ts, tf] */
     double tol;             /* flagging tolerance */
     int32_t flag_every;     /* flag after every flag_every accepted steps (>= 1) */
-    int32_t reserved;
+    int32_t full_frames;    /* 0: the flag passes skip, per cell, the snapshots that are exactly zero
+                               there (adj_frame_bounds); 1: they read every snapshot in full (same results) */
     double *frames;         /* device, (K+1)*ncomp*ny*pitch doubles of the adjoint grid (output) */
     swe_fields q_out;       /* device, final forward state (output) */
     int8_t *flags_at;       /* device, (K+1)*ny*pitch: flags at t0 + j ds; nullable */

@@ -334,6 +334,7 @@ static swe_status advance_impl(const swe_grid *grid, const swe_params *prm, cons
         fp.sea_level = prm->sea_level; fp.dry_tol = prm->dry_tol; fp.tol = fl->tol;
         fp.B = B; fp.frames = fl->frames;
         fp.flag_acc = fl->flag_acc; fp.maxip_acc = fl->maxip_acc;
+        fp.bounds = fl->bounds;
         if (fl->adj_grid && (st = setup_interp(fp, grid, fl->adj_grid, fl->adj_B)) != SWE_OK) return st;
         std::memset(&fc, 0, sizeof fc);
         fc.ctl = ctl; fc.K = fl->K; fc.flag_every = fl->flag_every;
@@ -415,7 +416,7 @@ static swe_status setup_interp(swe::FlagParams &f, const swe_grid *grid, const s
 static swe_status flag_common(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
                               const swe_grid *ag, const double *aB, const double *frames, int32_t K, int32_t k_lo,
                               int32_t k_hi, double tol, int8_t *flags, double *maxip, int8_t *flag_acc,
-                              double *maxip_acc, void *stream)
+                              double *maxip_acc, const int32_t *bounds, void *stream)
 {
     swe_status st;
     if ((st = check_grid(grid)) != SWE_OK) return st;
@@ -436,6 +437,7 @@ static swe_status flag_common(const swe_grid *grid, const swe_params *prm, const
     f.sea_level = prm->sea_level; f.dry_tol = prm->dry_tol; f.tol = tol;
     f.B = B; f.q0 = q.f0; f.q1 = q.f1; f.q2 = q.f2; f.frames = frames;
     f.flags = flags; f.maxip = maxip; f.flag_acc = flag_acc; f.maxip_acc = maxip_acc;
+    f.bounds = bounds;
     if (ag && (st = setup_interp(f, grid, ag, aB)) != SWE_OK) return st;
     HIP_TRY(swe::launch_flag(f, (hipStream_t)stream));
     return SWE_OK;
@@ -443,20 +445,32 @@ static swe_status flag_common(const swe_grid *grid, const swe_params *prm, const
 
 swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
                     const double *frames, int32_t K, int32_t k_lo, int32_t k_hi, double tol,
-                    int8_t *flags, double *maxip, int8_t *flag_acc, double *maxip_acc, void *stream)
+                    int8_t *flags, double *maxip, int8_t *flag_acc, double *maxip_acc, const int32_t *bounds,
+                    void *stream)
 {
     return flag_common(grid, prm, B, q, nullptr, nullptr, frames, K, k_lo, k_hi, tol, flags, maxip, flag_acc,
-                       maxip_acc, stream);
+                       maxip_acc, bounds, stream);
+}
+
+swe_status adj_frame_bounds(const swe_grid *grid, const double *frames, int32_t K, int32_t *bounds, void *stream)
+{
+    swe_status st;
+    if ((st = check_grid(grid)) != SWE_OK) return st;
+    if (!frames || !bounds) return fail(SWE_E_INVAL, "frames or bounds is NULL");
+    if (K < 0) return fail(SWE_E_INVAL, "K must be >= 0");
+    HIP_TRY(swe::launch_frame_bounds(frames, grid->nx, grid->ny, grid->pitch, grid->ny > 1 ? 3 : 2, K, bounds,
+                                     (hipStream_t)stream));
+    return SWE_OK;
 }
 
 swe_status adj_flag_interp(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q,
                            const swe_grid *adj_grid, const double *adj_B, const double *frames, int32_t K,
                            int32_t k_lo, int32_t k_hi, double tol, int8_t *flags, double *maxip, int8_t *flag_acc,
-                           double *maxip_acc, void *stream)
+                           double *maxip_acc, const int32_t *bounds, void *stream)
 {
     if (!adj_grid) return fail(SWE_E_INVAL, "adj_grid is NULL");
     return flag_common(grid, prm, B, q, adj_grid, adj_B, frames, K, k_lo, k_hi, tol, flags, maxip, flag_acc,
-                       maxip_acc, stream);
+                       maxip_acc, bounds, stream);
 }
 
 swe_status swe_surface_flag(const swe_grid *grid, const swe_params *prm, const double *B, swe_fields q, double tol,
@@ -483,6 +497,7 @@ struct Workspace {
     swe_scalars *sc;
     unsigned long long *speed;
     swe_ctl *ctl;
+    int32_t *bounds;          // non-zero boxes of the snapshots
     size_t bytes;
 };
 
@@ -501,6 +516,7 @@ static swe_status check_problem(const swe_problem *pb)
         return fail(SWE_E_INVAL, "need finite t0 < tf");
     if (!(pb->ts >= pb->t0 && pb->ts <= pb->tf)) return fail(SWE_E_INVAL, "need t0 <= ts <= tf");
     if (pb->flag_every < 1) return fail(SWE_E_INVAL, "flag_every must be >= 1");
+    if (pb->full_frames != 0 && pb->full_frames != 1) return fail(SWE_E_INVAL, "full_frames must be 0 or 1");
     if (!(pb->target_R > 0.0)) return fail(SWE_E_INVAL, "target radius must be > 0");
     if (pb->adj_grid.nx != 0) {
         if ((st = check_grid(&pb->adj_grid)) != SWE_OK) return st;
@@ -535,6 +551,8 @@ static size_t ws_layout(const swe_problem *pb, Workspace *w, char *base)
     off = align256(off + sizeof(unsigned long long));
     if (w) w->ctl = (swe_ctl *)(base + off);
     off = align256(off + sizeof(swe_ctl));
+    if (w) w->bounds = (int32_t *)(base + off);
+    off = align256(off + (size_t)4 * (pb->K + 1) * sizeof(int32_t));
     if (w) w->bytes = off;
     return off;
 }
@@ -618,6 +636,13 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         }
     }
 
+    // the snapshots' non-zero boxes: outside them the flag passes have nothing to read
+    const int32_t *bounds = nullptr;
+    if (!pb->full_frames) {
+        if ((st = adj_frame_bounds(AG, pb->frames, K, w.bounds, stream)) != SWE_OK) return st;
+        bounds = w.bounds;
+    }
+
     // ---- phase B: forward with flagging, stepped and flagged on the device;
     // the host only waits once per output segment
     swe_fields cur = A, nxt = Bf;
@@ -627,7 +652,7 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         if ((st = adj_window(pb->t0, pb->t0, pb->ts, pb->tf, K, &lo, &hi)) != SWE_OK) return st;
         int8_t *fl0 = pb->flags_at ? pb->flags_at : w.flags;
         if ((st = flag_common(G, P, pb->B, cur, interp ? AG : nullptr, AB, pb->frames, K, lo, hi, pb->tol, fl0,
-                              nullptr, pb->flag_acc, pb->maxip_acc, stream)) != SWE_OK)
+                              nullptr, pb->flag_acc, pb->maxip_acc, bounds, stream)) != SWE_OK)
             return st;
         if (pb->surface_flags_at &&
             (st = swe_surface_flag(G, P, pb->B, cur, pb->surface_tol, pb->surface_flags_at, nullptr, stream)) !=
@@ -650,6 +675,7 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     fl.maxip_acc = pb->maxip_acc;
     fl.adj_grid = interp ? AG : nullptr;
     fl.adj_B = interp ? AB : nullptr;
+    fl.bounds = bounds;
     swe_ctl hc;
     for (int j = 1; j <= K; ++j) {
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;

@@ -29,6 +29,10 @@ struct FlagParams {
     int anx, any, apitch;
     double ax_lo, ay_lo, adx, ady;
     const double *aB;
+    // per snapshot the box (i_lo, i_hi, j_lo, j_hi) holding its non-zero
+    // cells (on the snapshots' grid), or null: snapshots outside a cell's box
+    // contribute |0| = 0 and are skipped
+    const int *bounds;
 };
 
 // Device-side flag scheduling after a controlled step attempt.
@@ -61,6 +65,8 @@ inline bool params_in_range(const swe_params *p)
 
 hipError_t launch_step(int model, const KParams &P, hipStream_t s);
 hipError_t launch_flag(const FlagParams &F, hipStream_t s);
+hipError_t launch_frame_bounds(const double *frames, int nx, int ny, int pitch, int ncomp, int K, int *bounds,
+                               hipStream_t s);
 hipError_t launch_surface_flag(const CellParams &C, const double *q0, double tol, int nonlinear, int8_t *flags,
                                int8_t *flag_acc, hipStream_t s);
 hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s);

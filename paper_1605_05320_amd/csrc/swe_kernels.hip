@@ -436,11 +436,18 @@ __device__ __forceinline__ void march_epilogue(const KParams &P, int lane, doubl
         sb = wave_sum(nbad);
     }
     if (lane == 0) {
-        if (sc && P.n_clamped) atomicAdd(P.n_clamped, sc);
-        if (sb && P.n_nonfinite) atomicAdd(P.n_nonfinite, sb);
-        if (P.cfl_bits)
-            atomicMax(P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0),
-                      (unsigned long long)__double_as_longlong(cfl));
+        unsigned long long *line =
+            P.cfl_bits ? P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0)
+                       : nullptr;
+        if (P.counts_in_ring) {
+            // controlled attempt: counted once its acceptance is known
+            if (sc) atomicAdd(line + 1, (unsigned long long)sc);
+            if (sb) atomicAdd(line + 2, (unsigned long long)sb);
+        } else {
+            if (sc && P.n_clamped) atomicAdd(P.n_clamped, sc);
+            if (sb && P.n_nonfinite) atomicAdd(P.n_nonfinite, sb);
+        }
+        if (line) atomicMax(line, (unsigned long long)__double_as_longlong(cfl));
     }
 }
 
@@ -546,8 +553,9 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
     bool ran = false;
     for (int a = 0; a < n_steps && !S.done; ++a) {
         if (blockIdx.x == 0 && threadIdx.x < SWE_CTL_SPREAD)
-            __hip_atomic_store(&c->ring[(a + 1) % 3][threadIdx.x][0], 0ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int w = 0; w < 3; ++w)
+                __hip_atomic_store(&c->ring[(a + 1) % 3][threadIdx.x][w], 0ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         KParams Q = P;
         Q.dt = S.dt;
         if (S.cur) {
@@ -569,6 +577,15 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
             last_bits = v > last_bits ? v : last_bits;
         }
         S = ctl_apply(S, __longlong_as_double((long long)last_bits), P.cfl_desired, P.cfl_max);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && S.last_accepted) {
+            unsigned long long ncl = 0, nbad = 0;
+            for (int j = 0; j < SWE_CTL_SPREAD; ++j) {
+                ncl += __hip_atomic_load(&c->ring[a % 3][j][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                nbad += __hip_atomic_load(&c->ring[a % 3][j][2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            c->n_clamped = c->n_clamped + (int)ncl;
+            c->n_nonfinite = c->n_nonfinite + (int)nbad;
+        }
         ran = true;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -602,6 +619,7 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
     double FE[3], amE[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) { FE[k] = from_hi(F[k]); amE[k] = from_hi(x.am[k]); }
+    int nbad = 0;
     if (core) {
         double o[2];
 #pragma unroll
@@ -613,6 +631,7 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
             }
             o[k] = qv;
         }
+        if (!isfinite(o[0]) || !isfinite(o[1])) ++nbad;
         P.out0[i] = o[0];
         P.out1[i] = o[1];
     }
@@ -620,10 +639,7 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
     if (xedge_in)
 #pragma unroll
         for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nu * fabs(x.s[p]));
-    cfl = wave_max(cfl);
-    if (lane == 0 && P.cfl_bits)
-        atomicMax(P.cfl_bits + (P.cfl_spread > 1 ? (size_t)(blockIdx.x % P.cfl_spread) * P.cfl_stride : 0),
-                  (unsigned long long)__double_as_longlong(cfl));
+    march_epilogue(P, lane, cfl, 0, nbad);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,6 +685,7 @@ __global__ void k_ctl_finish(swe_ctl *c, int n, double cfl_desired, double cfl_m
     if (threadIdx.x != 0 || blockIdx.x != 0 || n < 1) return;
     unsigned long long bits = ring_bits(c, (n - 1) % 3);
     c->s = ctl_apply(c->slot[(n - 1) & 1], __longlong_as_double((long long)bits), cfl_desired, cfl_max);
+    add_counts_if_accepted(c, (n - 1) % 3, c->s);
     c->cfl_bits = bits;
     clear_ring(c);
 }
@@ -714,6 +731,11 @@ __device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size
             const double q2 = F.twod ? F.q2[k] : 0.0;
             const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
             for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
+                if (F.bounds) {
+                    // outside the snapshot's non-zero box: |<q, 0>| = 0 leaves m as it is
+                    const int *b = F.bounds + 4 * f;
+                    if (i < b[0] || i > b[1] || j < b[2] || j > b[3]) continue;
+                }
                 double ip = eta * fr[0] + q1 * fr[plane];
                 if (F.twod) ip = ip + q2 * fr[2 * plane];
                 m = dmax(m, fabs(ip));
@@ -743,6 +765,11 @@ __device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size
     const double ux = 1.0 - wx, uy = 1.0 - wy;
     const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * aplane;
     for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * aplane) {
+        if (F.bounds) {
+            // no interpolation corner inside the snapshot's non-zero box
+            const int *b = F.bounds + 4 * f;
+            if (i1 < b[0] || i0 > b[1] || j1 < b[2] || j0 > b[3]) continue;
+        }
         double v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -758,6 +785,51 @@ __device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size
         m = dmax(m, fabs(ip));
     }
     return m;
+}
+
+// Bounding box (i_lo, i_hi, j_lo, j_hi) of the cells of snapshot
+// blockIdx.y with a non-zero value in any plane (a NaN counts as non-zero);
+// an empty snapshot keeps (nx, -1, ny, -1) from k_bounds_init.
+__global__ void __launch_bounds__(256) k_bounds_init(int *bounds, int n_frames, int nx, int ny)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * n_frames) return;
+    const int w = t & 3;
+    bounds[t] = w == 0 ? nx : (w == 2 ? ny : -1);
+}
+
+__global__ void __launch_bounds__(256) k_frame_bounds(const double *frames, int nx, int ny, int pitch, int ncomp,
+                                                      int *bounds)
+{
+    const int k = blockIdx.y;
+    const size_t plane = (size_t)ny * pitch;
+    const double *f = frames + (size_t)k * ncomp * plane;
+    int ilo = nx, ihi = -1, jlo = ny, jhi = -1;
+    const long long n = (long long)nx * ny;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int j = (int)(idx / nx), i = (int)(idx - (long long)j * nx);
+        const size_t o = (size_t)j * pitch + i;
+        bool nz = false;
+        for (int c = 0; c < ncomp; ++c) nz = nz || !(f[c * plane + o] == 0.0);
+        if (nz) {
+            ilo = min(ilo, i); ihi = max(ihi, i);
+            jlo = min(jlo, j); jhi = max(jhi, j);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ilo = min(ilo, __shfl_xor(ilo, off, WAVE));
+        ihi = max(ihi, __shfl_xor(ihi, off, WAVE));
+        jlo = min(jlo, __shfl_xor(jlo, off, WAVE));
+        jhi = max(jhi, __shfl_xor(jhi, off, WAVE));
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0 && ihi >= 0) {
+        atomicMin(&bounds[4 * k + 0], ilo);
+        atomicMax(&bounds[4 * k + 1], ihi);
+        atomicMin(&bounds[4 * k + 2], jlo);
+        atomicMax(&bounds[4 * k + 3], jhi);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_flag(FlagParams F)
@@ -1027,6 +1099,18 @@ hipError_t launch_count_diff(const double *a, const double *b, long long n, int 
 hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s)
 {
     hipLaunchKernelGGL(k_flag_ctl, dim3(grid_cells((long long)F.nx * F.ny)), dim3(256), 0, s, F, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_frame_bounds(const double *frames, int nx, int ny, int pitch, int ncomp, int K, int *bounds,
+                               hipStream_t s)
+{
+    const int nf = K + 1;
+    hipLaunchKernelGGL(k_bounds_init, dim3((4 * nf + 255) / 256), dim3(256), 0, s, bounds, nf, nx, ny);
+    long long blocks = ((long long)nx * ny + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    hipLaunchKernelGGL(k_frame_bounds, dim3((unsigned)blocks, (unsigned)nf), dim3(256), 0, s, frames, nx, ny, pitch,
+                       ncomp, bounds);
     return hipGetLastError();
 }
 

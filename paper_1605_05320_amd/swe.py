@@ -48,7 +48,7 @@ class swe_problem(C.Structure):
                 ("target_xc", C.c_double), ("target_yc", C.c_double), ("target_R", C.c_double),
                 ("target_shape", C.c_int32), ("K", C.c_int32),
                 ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
-                ("flag_every", C.c_int32), ("reserved", C.c_int32),
+                ("flag_every", C.c_int32), ("full_frames", C.c_int32),
                 ("frames", C.c_void_p), ("q_out", swe_fields), ("flags_at", C.c_void_p),
                 ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
                 ("surface_tol", C.c_double), ("surface_flags_at", C.c_void_p),
@@ -113,7 +113,7 @@ def lib():
                      "adj_flag", "swe_run", "swe_ctl_set", "swe_ctl_retarget", "swe_advance",
                      "swe_level_advance", "swe_level_schedule", "swe_level_tune", "swe_advance_flagged",
                      "swe_serve", "swe_surface_flag", "adj_flag_interp", "swe_cluster", "swe_prolong",
-                     "swe_run_static"):
+                     "swe_run_static", "adj_frame_bounds"):
             getattr(L, name).restype = C.c_int
         L.swe_run_workspace_bytes.restype = C.c_size_t
         L.swe_serve_footprint.restype = C.c_size_t
@@ -212,18 +212,25 @@ def adj_window(t, t0, ts, tf, K):
 
 
 def adj_flag(grid: Grid, prm: Params, B, q, frames, K, k_lo, k_hi, tol, flags=None, maxip=None,
-             flag_acc=None, maxip_acc=None, stream=None):
+             flag_acc=None, maxip_acc=None, stream=None, bounds=None):
     _check(lib().adj_flag(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), _ptr(frames),
                           C.c_int32(K), C.c_int32(k_lo), C.c_int32(k_hi), C.c_double(tol),
-                          _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc), _stream(stream)))
+                          _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc), _ptr(bounds),
+                          _stream(stream)))
+
+
+def adj_frame_bounds(grid: Grid, frames, K, bounds, stream=None):
+    """Non-zero boxes (i_lo, i_hi, j_lo, j_hi) of snapshots 0..K into the
+    int32 device tensor `bounds` (4*(K+1) entries)."""
+    _check(lib().adj_frame_bounds(C.byref(grid.c()), _ptr(frames), C.c_int32(K), _ptr(bounds), _stream(stream)))
 
 
 def adj_flag_interp(grid: Grid, prm: Params, B, q, adj_grid: Grid, adj_B, frames, K, k_lo, k_hi, tol, flags=None,
-                    maxip=None, flag_acc=None, maxip_acc=None, stream=None):
+                    maxip=None, flag_acc=None, maxip_acc=None, stream=None, bounds=None):
     _check(lib().adj_flag_interp(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(q), C.byref(adj_grid.c()),
                                  _ptr(adj_B), _ptr(frames), C.c_int32(K), C.c_int32(k_lo), C.c_int32(k_hi),
                                  C.c_double(tol), _ptr(flags), _ptr(maxip), _ptr(flag_acc), _ptr(maxip_acc),
-                                 _stream(stream)))
+                                 _ptr(bounds), _stream(stream)))
 
 
 def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=None, stream=None):
@@ -233,8 +240,10 @@ def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=No
 
 def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, frames, q_out,
                  flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS,
-                 surface_tol=0.0, surface_flags_at=None, adj_grid: Grid = None, adj_B=None) -> swe_problem:
+                 surface_tol=0.0, surface_flags_at=None, adj_grid: Grid = None, adj_B=None,
+                 full_frames=0) -> swe_problem:
     pb = swe_problem()
+    pb.full_frames = full_frames
     pb.grid = grid.c()
     pb.params = prm.c()
     pb.B, pb.eta0 = B.data_ptr(), eta0.data_ptr()
@@ -309,18 +318,19 @@ class swe_flagging(C.Structure):
     _fields_ = [("frames", C.c_void_p), ("K", C.c_int32), ("flag_every", C.c_int32),
                 ("t0", C.c_double), ("ts", C.c_double), ("tf", C.c_double), ("tol", C.c_double),
                 ("flags_final", C.c_void_p), ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
-                ("adj_grid", C.POINTER(swe_grid)), ("adj_B", C.c_void_p)]
+                ("adj_grid", C.POINTER(swe_grid)), ("adj_B", C.c_void_p), ("bounds", C.c_void_p)]
 
 
 def swe_advance_flagged(grid: Grid, prm: Params, B, a, b, ctl, n_attempts: int, frames, K, flag_every,
                         t0, ts, tf, tol, flags_final=None, flag_acc=None, maxip_acc=None, adj_grid: Grid = None,
-                        adj_B=None, stream=None):
+                        adj_B=None, stream=None, bounds=None):
     ag = None if adj_grid is None else C.pointer(adj_grid.c())
     fl = swe_flagging(frames.data_ptr(), K, flag_every, t0, ts, tf, tol,
                       None if flags_final is None else flags_final.data_ptr(),
                       None if flag_acc is None else flag_acc.data_ptr(),
                       None if maxip_acc is None else maxip_acc.data_ptr(),
-                      ag, None if adj_B is None else adj_B.data_ptr())
+                      ag, None if adj_B is None else adj_B.data_ptr(),
+                      None if bounds is None else bounds.data_ptr())
     _check(lib().swe_advance_flagged(C.byref(grid.c()), C.byref(prm.c()), _ptr(B), fields(a), fields(b),
                                      _ptr(ctl), C.c_int32(n_attempts), C.byref(fl), _stream(stream)))
 
