@@ -415,6 +415,23 @@ def secondary(S, torch, I, np, f64):
     g, p, B, q, K, fl, acc, macc = (ctx[k] for k in ("g", "p", "B", "q", "K", "fl", "acc", "macc"))
     out["flag_512_w34_us"] = t * 1e6
     out["flag_512_w34_GBs"] = fbytes / t / 1e9
+    # the same window at 1024^2: 34 snapshots of 25 MB, 855 MB in all, more
+    # than the 256 MB last-level cache holds, so every pass streams from HBM
+    n1 = 1024
+    b1 = I.basin(n1, 3)
+    g1 = S.Grid(n1, n1, b1.grid.dx, b1.grid.dy)
+    B1 = torch.tensor(b1.B, **f64)
+    fr1 = torch.randn(K + 1, 3, n1, n1, **f64) * 1e-3
+    q1 = [torch.tensor(np.maximum(0.0, -b1.B), **f64), torch.zeros(n1, n1, **f64), torch.zeros(n1, n1, **f64)]
+    fl1 = torch.empty(n1, n1, dtype=torch.int8, device=B.device)
+    acc1 = torch.zeros(n1, n1, dtype=torch.int8, device=B.device)
+    macc1 = torch.zeros(n1, n1, **f64)
+    t = min(_time_events(torch, lambda: S.adj_flag(g1, p, B1, q1, fr1, K, 30, 63, 1e-4, fl1, None, acc1, macc1),
+                         10) for _ in range(3))
+    out["flag_1024_w34_us"] = t * 1e6
+    out["flag_1024_w34_GBs"] = n1 * n1 * FLAG_BYTES_PER_CELL_W34 / t / 1e9
+    del fr1, q1, B1, fl1, acc1, macc1
+    torch.cuda.empty_cache()
     # the same pass with the snapshots on a 256^2 adjoint grid (bilinear
     # interpolation at every cell and snapshot)
     nc = n // 2
@@ -457,6 +474,13 @@ def secondary(S, torch, I, np, f64):
     out.update(run_bench(S, torch, I, np, f64))
     out.update(level_bench(S, torch, I, np, f64))
     return out
+
+
+def _box_fraction(bnd, K, nx, ny):
+    """Mean over the snapshots of the fraction of the grid inside each one's box."""
+    b = bnd.view(K + 1, 4).cpu().tolist()
+    a = [(r[1] - r[0] + 1) * (r[3] - r[2] + 1) if r[1] >= r[0] else 0 for r in b]
+    return round(sum(a) / (len(a) * nx * ny), 4)
 
 
 def run_bench(S, torch, I, np, f64):
@@ -503,6 +527,46 @@ def run_bench(S, torch, I, np, f64):
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         cells = n * ny
+        if ny > 1:
+            # the same run reading every snapshot in full in every flag pass
+            pf = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc,
+                                full_frames=1)
+            acc.zero_(); macc.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.swe_run(pf, ws)
+            torch.cuda.synchronize()
+            out[tag + "_full_frames_s"] = round(time.perf_counter() - t, 4)
+            # single flag passes over this run's snapshots: the window of the
+            # first output times (snapshots 32..64, spread over the basin) and of
+            # the last ones (0..2, near the target), with and without the boxes
+            bnd = torch.empty(4 * (K + 1), dtype=torch.int32, device=B.device)
+            S.adj_frame_bounds(g, frames, K, bnd)
+            fl = torch.empty(ny, n, dtype=torch.int8, device=B.device)
+            for lo, hi in ((32, 64), (0, 2)):
+                for use in (False, True):
+                    tt = _time_events(torch, lambda: S.adj_flag(g, prm, B, q, frames, K, lo, hi, tol, fl,
+                                                                bounds=bnd if use else None), 20)
+                    out[f"flag_512_snapshots_{lo}_{hi}_{'boxes' if use else 'full'}_us"] = round(tt * 1e6, 2)
+            out[tag + "_snapshot_box_fraction"] = _box_fraction(bnd, K, n, ny)
+            # the paper's own target, the indicator of a disk (Sec. 6): its
+            # snapshots are exactly zero outside the adjoint's numerical domain
+            # of dependence, so the boxes are tighter than a Gaussian's
+            for full in (0, 1):
+                pd = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc,
+                                    shape=S.DISK, full_frames=full)
+                acc.zero_(); macc.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                S.swe_run(pd, ws)
+                torch.cuda.synchronize()
+                out[tag + ("_disk_full_frames_s" if full else "_disk_s")] = round(time.perf_counter() - t, 4)
+            S.adj_frame_bounds(g, frames, K, bnd)
+            out[tag + "_disk_snapshot_box_fraction"] = _box_fraction(bnd, K, n, ny)
+            for use in (False, True):
+                tt = _time_events(torch, lambda: S.adj_flag(g, prm, B, q, frames, K, 32, 64, tol, fl,
+                                                            bounds=bnd if use else None), 20)
+                out[f"flag_512_disk_snapshots_32_64_{'boxes' if use else 'full'}_us"] = round(tt * 1e6, 2)
         out[tag] = {"s": round(el, 4), "adjoint_steps": r.n_adj_steps, "forward_steps": r.n_fwd_steps,
                     "flag_passes": r.n_flag_calls, "flagged_cells": int(acc.sum().item()),
                     "cell_updates_per_s": cells * (r.n_adj_steps + r.n_fwd_steps) / el,
@@ -682,7 +746,30 @@ def level_bench(S, torch, I, np, f64, n_patches=3000, n_steps=100, seed=4):
     torch.cuda.current_stream().wait_stream(cs)
     torch.cuda.synchronize()
     per_patch = _time_events(torch, graph.replay, 5)
+    # the same level with waves on every edge (a centimetre of seeded noise on
+    # the surface of every wet cell): a refined level sits where the waves are,
+    # while the patches above are mostly sea at rest (the zero-flux fast path)
+    noise = torch.tensor(np.random.default_rng(seed + 11).uniform(-0.01, 0.01, ncell), **f64)
+    eta_b = eta + noise
+    spd.zero_()
+    for k in range(n_patches):
+        o, n = tab[k].offset, tab[k].nx * tab[k].ny
+        g = S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy)
+        q = [x[o:o + n] for x in wa]
+        S.swe_init(g, prm, B[o:o + n], eta_b[o:o + n], q)
+        S.swe_max_speed(g, prm, B[o:o + n], q, 0, spd)
+    dtb = prm.cfl_desired / float(spd.view(torch.float64).item())
+    S.swe_ctl_set(ctl, 0.0, dtb, 1.0e300, 0)
+    torch.cuda.synchronize()
+    e0.record()
+    S.level_advance(levels[lv], prm, B, wa, wb, ctl, n_steps, pers)
+    e1.record()
+    torch.cuda.synchronize()
+    busy_ms = e0.elapsed_time(e1)
+    cb = S.read_ctl(ctl)
     return {"level_patches": n_patches, "level_cells": ncell,
+            "level_busy_ms_per_step": busy_ms / n_steps,
+            "level_busy_cell_updates_per_s": ncell * cb.n_accepted / (busy_ms * 1e-3),
             "level_candidates_us_per_step": {names[(l, p)]: round(u, 2) for l, p, u in entries if u >= 0},
             "level_schedule": names[(lv, pers)],
             "level_lane_occupancy": {lnames[k]: round(levels[k].lane_occupancy, 3) for k in range(len(levels))},
@@ -804,9 +891,19 @@ def cpu_baseline(b, n, budget_s):
     el = time.perf_counter() - t
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     del np
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n * n * m / el, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model,
             "sample": f"{m} steps of the {n}x{n} basin after 1 warm-up step ({el:.1f} s), "
-                      f"OpenMP over rows"}
+                      f"OpenMP over rows on {threads} threads of {model}"}
 
 
 if __name__ == "__main__":
