@@ -711,80 +711,161 @@ __device__ __forceinline__ void axis_weights(double x, double x_lo, double d, in
     w = ww < 0.0 ? 0.0 : (ww > 1.0 ? 1.0 : ww);
 }
 
+// Skipping snapshots that are exactly zero.  A snapshot contributes
+// |<q, 0>| = 0 wherever it is zero, which leaves the maximum as it is (q
+// finite).  The decision is taken per wavefront, for the rectangle of
+// snapshot-grid indices its 64 cells read: a snapshot whose non-zero box
+// misses the rectangle is skipped by the whole wavefront, the others are read
+// by every lane (reading zeros where a lane lies outside the box).  Lane l
+// tests snapshot base + l, so one ballot covers 64 snapshots of the window.
+struct IdxRect { int i0, i1, j0, j1; };
+
+__device__ __forceinline__ unsigned long long window_mask(const int *bounds, int base, int k_hi, const IdxRect &r)
+{
+    const int f = base + (int)(threadIdx.x & (WAVE - 1));
+    bool hit = false;
+    if (f <= k_hi) {
+        const int *b = bounds + 4 * f;
+        const int b0 = b[0], b1 = b[1], b2 = b[2], b3 = b[3];   // four loads in flight together
+        hit = (r.i1 >= b0) & (r.i0 <= b1) & (r.j1 >= b2) & (r.j0 <= b3);
+    }
+    return __ballot(hit);
+}
+
+// m = max(m, |dot(f)|) over the snapshots f = base + s of the bits s of
+// `mask`, in increasing order, four at a time so that their loads are in
+// flight together; a short last group repeats its last snapshot, which leaves
+// the maximum as it is.
+template <class Dot>
+__device__ __forceinline__ double max_over_mask(unsigned long long mask, int base, const Dot &dot, double m)
+{
+    while (mask) {
+        int f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (mask) {
+                f[u] = base + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+            } else {
+                f[u] = f[u > 0 ? u - 1 : 0];
+            }
+        }
+        double ip[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ip[u] = dot(f[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m = dmax(m, fabs(ip[u]));
+    }
+    return m;
+}
+
 // m = max over the window's snapshots of |<q, q^_k>| at cell (i, j) (storage
 // index k), 0 where the forward or the adjoint cell is dry.  With snapshots on
-// their own grid, q^_k is interpolated (bilinear in 2D, linear in 1D) at the
-// cell centre and the adjoint cell is the one containing the centre.
-__device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size_t k)
+// their own grid (INTERP), q^_k is interpolated (bilinear in 2D, linear in 1D)
+// at the cell centre and the adjoint cell is the one containing the centre.
+// Called by every lane of the wavefront (`live` false past the last cell,
+// with k a valid index); with boxes, r is the wavefront's rectangle.  The
+// snapshots are visited in increasing order either way.
+template <bool TWOD, bool INTERP>
+__device__ __forceinline__ double flag_m(const FlagParams &F, int i, int j, size_t k, bool live, IdxRect r)
 {
     const double B = F.B[k];
     const double q0 = F.q0[k];
-    double m = 0.0;
-    if (!F.interp) {
-        const size_t plane = (size_t)F.ny * F.pitch;
-        const double hb = dmax(0.0, F.sea_level - B);
-        const bool adj_wet = hb > F.dry_tol;
-        const bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : adj_wet;
-        if (adj_wet && fwd_wet) {
-            const double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
-            const double q1 = F.q1[k];
-            const double q2 = F.twod ? F.q2[k] : 0.0;
-            const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * plane + k;
-            for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * plane) {
-                if (F.bounds) {
-                    // outside the snapshot's non-zero box: |<q, 0>| = 0 leaves m as it is
-                    const int *b = F.bounds + 4 * f;
-                    if (i < b[0] || i > b[1] || j < b[2] || j > b[3]) continue;
-                }
-                double ip = eta * fr[0] + q1 * fr[plane];
-                if (F.twod) ip = ip + q2 * fr[2 * plane];
-                m = dmax(m, fabs(ip));
-            }
-        }
-        return m;
-    }
-    const bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol) : (dmax(0.0, F.sea_level - B) > F.dry_tol);
-    const double x = F.x_lo + (i + 0.5) * F.dx;
-    int i0, ic, j0 = 0, jc = 0;
-    double wx, wy = 0.0;
-    axis_weights(x, F.ax_lo, F.adx, F.anx, i0, wx, ic);
-    if (F.twod) {
-        const double y = F.y_lo + (j + 0.5) * F.dy;
-        axis_weights(y, F.ay_lo, F.ady, F.any, j0, wy, jc);
-    }
-    const bool adj_wet = dmax(0.0, F.sea_level - F.aB[(size_t)jc * F.apitch + ic]) > F.dry_tol;
-    if (!(adj_wet && fwd_wet)) return 0.0;
     const double eta = F.nonlinear ? (q0 + B) - F.sea_level : q0;
-    const double q1 = F.q1[k];
-    const double q2 = F.twod ? F.q2[k] : 0.0;
-    const size_t aplane = (size_t)F.any * F.apitch;
-    const int i1 = F.anx >= 2 ? i0 + 1 : i0;
-    const int j1 = F.twod && F.any >= 2 ? j0 + 1 : j0;
-    const size_t k00 = (size_t)j0 * F.apitch + i0, k10 = (size_t)j0 * F.apitch + i1;
-    const size_t k01 = (size_t)j1 * F.apitch + i0, k11 = (size_t)j1 * F.apitch + i1;
-    const double ux = 1.0 - wx, uy = 1.0 - wy;
-    const double *fr = F.frames + (size_t)F.k_lo * F.ncomp * aplane;
-    for (int f = F.k_lo; f <= F.k_hi; ++f, fr += (size_t)F.ncomp * aplane) {
-        if (F.bounds) {
-            // no interpolation corner inside the snapshot's non-zero box
-            const int *b = F.bounds + 4 * f;
-            if (i1 < b[0] || i0 > b[1] || j1 < b[2] || j0 > b[3]) continue;
+    double m = 0.0;
+    const size_t plane = INTERP ? (size_t)F.any * F.apitch : (size_t)F.ny * F.pitch;
+    const size_t fstride = (size_t)F.ncomp * plane;
+    bool adj_wet;
+    // cell offsets in the snapshot planes: the cell itself, or the four
+    // interpolation corners and their weights
+    size_t k00 = k, k10 = k, k01 = k, k11 = k;
+    double ux = 1.0, wx = 0.0, uy = 1.0, wy = 0.0;
+    if (!INTERP) {
+        adj_wet = dmax(0.0, F.sea_level - B) > F.dry_tol;
+    } else {
+        const double x = F.x_lo + (i + 0.5) * F.dx;
+        int i0, ic, j0 = 0, jc = 0;
+        axis_weights(x, F.ax_lo, F.adx, F.anx, i0, wx, ic);
+        if (TWOD) {
+            const double y = F.y_lo + (j + 0.5) * F.dy;
+            axis_weights(y, F.ay_lo, F.ady, F.any, j0, wy, jc);
         }
+        adj_wet = dmax(0.0, F.sea_level - F.aB[(size_t)jc * F.apitch + ic]) > F.dry_tol;
+        const int i1 = F.anx >= 2 ? i0 + 1 : i0;
+        const int j1 = TWOD && F.any >= 2 ? j0 + 1 : j0;
+        k00 = (size_t)j0 * F.apitch + i0;
+        k10 = (size_t)j0 * F.apitch + i1;
+        k01 = (size_t)j1 * F.apitch + i0;
+        k11 = (size_t)j1 * F.apitch + i1;
+        ux = 1.0 - wx;
+        uy = 1.0 - wy;
+    }
+    const bool fwd_wet = F.nonlinear ? (q0 > F.dry_tol)
+                                     : (INTERP ? dmax(0.0, F.sea_level - B) > F.dry_tol : adj_wet);
+    const bool go = live && adj_wet && fwd_wet;
+    const double q1 = go ? F.q1[k] : 0.0;
+    const double q2 = TWOD && go ? F.q2[k] : 0.0;
+    auto dot = [&](int f) {
+        const double *fr = F.frames + (size_t)f * fstride;
         double v[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c == 2 && !F.twod) { v[c] = 0.0; continue; }
-            const double *p = fr + (size_t)c * aplane;
-            if (F.twod)
+        for (int c = 0; c < (TWOD ? 3 : 2); ++c) {
+            const double *p = fr + (size_t)c * plane;
+            if (!INTERP)
+                v[c] = p[k00];
+            else if (TWOD)
                 v[c] = uy * (ux * p[k00] + wx * p[k10]) + wy * (ux * p[k01] + wx * p[k11]);
             else
                 v[c] = ux * p[k00] + wx * p[k10];
         }
         double ip = eta * v[0] + q1 * v[1];
-        if (F.twod) ip = ip + q2 * v[2];
-        m = dmax(m, fabs(ip));
+        if (TWOD) ip = ip + q2 * v[2];
+        return ip;
+    };
+    for (int base = F.k_lo; base <= F.k_hi; base += WAVE) {
+        unsigned long long mask;
+        if (F.bounds) {
+            mask = window_mask(F.bounds, base, F.k_hi, r);
+        } else {
+            const int nb = F.k_hi - base + 1;
+            mask = nb >= WAVE ? ~0ull : (1ull << nb) - 1;
+        }
+        if (go) m = max_over_mask(mask, base, dot, m);
     }
     return m;
+}
+
+// The rectangle of snapshot-grid indices read by the wavefront whose cells
+// are the flat indices wb .. min(wb + 63, n - 1) (row-major, nx per row): the
+// cells themselves, or with snapshots on their own grid the interpolation
+// corners of those cells (monotone in the cell centre along each axis).
+__device__ __forceinline__ IdxRect wave_rect(const FlagParams &F, long long wb, long long n)
+{
+    const long long last = (wb + WAVE < n ? wb + WAVE : n) - 1;
+    IdxRect r;
+    r.j0 = (int)(wb / F.nx);
+    r.j1 = (int)(last / F.nx);
+    if (r.j0 == r.j1) {
+        r.i0 = (int)(wb - (long long)r.j0 * F.nx);
+        r.i1 = (int)(last - (long long)r.j1 * F.nx);
+    } else {
+        r.i0 = 0;
+        r.i1 = F.nx - 1;
+    }
+    if (!F.interp) return r;
+    int a, c;
+    double w;
+    IdxRect s;
+    axis_weights(F.x_lo + (r.i0 + 0.5) * F.dx, F.ax_lo, F.adx, F.anx, s.i0, w, c);
+    axis_weights(F.x_lo + (r.i1 + 0.5) * F.dx, F.ax_lo, F.adx, F.anx, a, w, c);
+    s.i1 = F.anx >= 2 ? a + 1 : a;
+    s.j0 = s.j1 = 0;
+    if (F.twod) {
+        axis_weights(F.y_lo + (r.j0 + 0.5) * F.dy, F.ay_lo, F.ady, F.any, s.j0, w, c);
+        axis_weights(F.y_lo + (r.j1 + 0.5) * F.dy, F.ay_lo, F.ady, F.any, a, w, c);
+        s.j1 = F.any >= 2 ? a + 1 : a;
+    }
+    return s;
 }
 
 // Bounding box (i_lo, i_hi, j_lo, j_hi) of the cells of snapshot
@@ -832,14 +913,20 @@ __global__ void __launch_bounds__(256) k_frame_bounds(const double *frames, int 
     }
 }
 
+template <bool TWOD, bool INTERP>
 __global__ void __launch_bounds__(256) k_flag(FlagParams F)
 {
     const long long n = (long long)F.nx * F.ny;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-         idx += (long long)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    // whole wavefronts step through the cells (the snapshot masks are ballots)
+    for (long long wb = (long long)blockIdx.x * blockDim.x + (threadIdx.x - lane); wb < n;
+         wb += (long long)gridDim.x * blockDim.x) {
+        const bool live = wb + lane < n;
+        const long long idx = live ? wb + lane : wb;
         int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
         size_t k = (size_t)j * F.pitch + i;
-        const double m = flag_m(F, i, j, k);
+        const double m = flag_m<TWOD, INTERP>(F, i, j, k, live, F.bounds ? wave_rect(F, wb, n) : IdxRect{0, 0, 0, 0});
+        if (!live) continue;
         int8_t fl = m > F.tol ? 1 : 0;
         if (F.flags) F.flags[k] = fl;
         if (F.maxip) F.maxip[k] = m;
@@ -878,6 +965,7 @@ __device__ __forceinline__ bool dev_window(double t, double t0, double ts, doubl
 // Courant number; if it was accepted and either reached the segment's output
 // time or its accepted-step count is a multiple of flag_every, flag the new
 // state (in plane set a or b according to the new cur) at the new time.
+template <bool TWOD, bool INTERP>
 __global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
 {
     swe_ctl *c = C.ctl;
@@ -895,11 +983,15 @@ __global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
     else       { F.q0 = C.a0; F.q1 = C.a1; F.q2 = C.a2; }
     F.flags = S.done ? C.flags_final : nullptr;
     const long long n = (long long)F.nx * F.ny;
-    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
-         idx += (long long)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (long long wb = (long long)blockIdx.x * blockDim.x + (threadIdx.x - lane); wb < n;
+         wb += (long long)gridDim.x * blockDim.x) {
+        const bool live = wb + lane < n;
+        const long long idx = live ? wb + lane : wb;
         int j = (int)(idx / F.nx), i = (int)(idx - (long long)j * F.nx);
         size_t k = (size_t)j * F.pitch + i;
-        const double m = flag_m(F, i, j, k);
+        const double m = flag_m<TWOD, INTERP>(F, i, j, k, live, F.bounds ? wave_rect(F, wb, n) : IdxRect{0, 0, 0, 0});
+        if (!live) continue;
         int8_t fl = m > F.tol ? 1 : 0;
         if (F.flags) F.flags[k] = fl;
         if (F.flag_acc) F.flag_acc[k] = (int8_t)(F.flag_acc[k] | fl);
@@ -1098,7 +1190,13 @@ hipError_t launch_count_diff(const double *a, const double *b, long long n, int 
 
 hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flag_ctl, dim3(grid_cells((long long)F.nx * F.ny)), dim3(256), 0, s, F, C);
+    const dim3 grid(grid_cells((long long)F.nx * F.ny));
+    switch ((F.twod ? 2 : 0) + (F.interp ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_flag_ctl<false, false>), grid, dim3(256), 0, s, F, C); break;
+    case 1: hipLaunchKernelGGL((k_flag_ctl<false, true>), grid, dim3(256), 0, s, F, C); break;
+    case 2: hipLaunchKernelGGL((k_flag_ctl<true, false>), grid, dim3(256), 0, s, F, C); break;
+    default: hipLaunchKernelGGL((k_flag_ctl<true, true>), grid, dim3(256), 0, s, F, C); break;
+    }
     return hipGetLastError();
 }
 
@@ -1116,7 +1214,13 @@ hipError_t launch_frame_bounds(const double *frames, int nx, int ny, int pitch, 
 
 hipError_t launch_flag(const FlagParams &F, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_flag, dim3(grid_cells((long long)F.nx * F.ny)), dim3(256), 0, s, F);
+    const dim3 grid(grid_cells((long long)F.nx * F.ny));
+    switch ((F.twod ? 2 : 0) + (F.interp ? 1 : 0)) {
+    case 0: hipLaunchKernelGGL((k_flag<false, false>), grid, dim3(256), 0, s, F); break;
+    case 1: hipLaunchKernelGGL((k_flag<false, true>), grid, dim3(256), 0, s, F); break;
+    case 2: hipLaunchKernelGGL((k_flag<true, false>), grid, dim3(256), 0, s, F); break;
+    default: hipLaunchKernelGGL((k_flag<true, true>), grid, dim3(256), 0, s, F); break;
+    }
     return hipGetLastError();
 }
 
