@@ -527,6 +527,18 @@ def run_bench(S, torch, I, np, f64):
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         cells = n * ny
+        if ny == 1:
+            # the same run with one launch per step and per flag pass
+            pl = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc,
+                                launch_per_step=1)
+            wl = torch.empty(S.swe_run_workspace_bytes(pl) // 8 + 64, **f64)
+            acc.zero_(); macc.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S.swe_run(pl, wl)
+            torch.cuda.synchronize()
+            out[tag + "_launch_per_step_s"] = round(time.perf_counter() - t, 4)
+            del wl
         if ny > 1:
             # the same run reading every snapshot in full in every flag pass
             pf = S.make_problem(g, prm, B, E, target, 0.0, ts, tf, K, tol, frames, q, None, acc, macc,

@@ -568,6 +568,11 @@ typedef struct {
                                grid (same dimension, its own resolution), frames have its size and
                                the flags interpolate the snapshots (adj_flag_interp) */
     const double *adj_B;    /* device bottom on adj_grid (with adj_grid) */
+    int32_t launch_per_step; /* 1D problems: 0 runs each phase of a grid of up to 3840 cells in one
+                                workgroup (state in LDS, one launch per phase, the flagged states
+                                recorded and flagged afterwards); 1 launches every step and flag
+                                pass as for 2D grids (same results bit for bit).  2D: ignored. */
+    int32_t reserved;
 } swe_problem;
 
 typedef struct {

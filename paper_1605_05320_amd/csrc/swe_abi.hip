@@ -498,6 +498,10 @@ struct Workspace {
     unsigned long long *speed;
     swe_ctl *ctl;
     int32_t *bounds;          // non-zero boxes of the snapshots
+    // 1D runs in one workgroup: the recorded states of a forward launch, their
+    // times and end-of-segment marks, their count, and m per record and cell
+    double *hist, *hist_t, *hist_m;
+    int *hist_done, *n_rec;
     size_t bytes;
 };
 
@@ -517,6 +521,8 @@ static swe_status check_problem(const swe_problem *pb)
     if (!(pb->ts >= pb->t0 && pb->ts <= pb->tf)) return fail(SWE_E_INVAL, "need t0 <= ts <= tf");
     if (pb->flag_every < 1) return fail(SWE_E_INVAL, "flag_every must be >= 1");
     if (pb->full_frames != 0 && pb->full_frames != 1) return fail(SWE_E_INVAL, "full_frames must be 0 or 1");
+    if (pb->launch_per_step != 0 && pb->launch_per_step != 1)
+        return fail(SWE_E_INVAL, "launch_per_step must be 0 or 1");
     if (!(pb->target_R > 0.0)) return fail(SWE_E_INVAL, "target radius must be > 0");
     if (pb->adj_grid.nx != 0) {
         if ((st = check_grid(&pb->adj_grid)) != SWE_OK) return st;
@@ -553,6 +559,20 @@ static size_t ws_layout(const swe_problem *pb, Workspace *w, char *base)
     off = align256(off + sizeof(swe_ctl));
     if (w) w->bounds = (int32_t *)(base + off);
     off = align256(off + (size_t)4 * (pb->K + 1) * sizeof(int32_t));
+    if (w) { w->hist = w->hist_t = w->hist_m = nullptr; w->hist_done = w->n_rec = nullptr; }
+    if (pb->grid.ny == 1 && pb->grid.nx <= swe::RUN1D_MAX_NX && !pb->launch_per_step) {
+        const size_t nx = (size_t)pb->grid.nx, R = swe::RUN1D_RECORDS;
+        if (w) w->hist = (double *)(base + off);
+        off = align256(off + R * 2 * nx * sizeof(double));
+        if (w) w->hist_m = (double *)(base + off);
+        off = align256(off + R * nx * sizeof(double));
+        if (w) w->hist_t = (double *)(base + off);
+        off = align256(off + R * sizeof(double));
+        if (w) w->hist_done = (int *)(base + off);
+        off = align256(off + R * sizeof(int));
+        if (w) w->n_rec = (int *)(base + off);
+        off = align256(off + sizeof(int));
+    }
     if (w) w->bytes = off;
     return off;
 }
@@ -625,14 +645,27 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     if ((st = adj_target(AG, P, AB, pb->target_xc, pb->target_yc, pb->target_R, pb->target_shape,
                          frame(0), stream)) != SWE_OK)
         return st;
-    for (int k = 1; k <= K; ++k) {
-        swe_fields src = frame(k - 1);
-        for (int sstep = 0; sstep < nsub; ++sstep) {
-            bool last = sstep == nsub - 1;
-            swe_fields dst = last ? frame(k) : ((sstep & 1) ? Bf : A);
-            if ((st = adj_step(AG, P, AB, src, dst, dt_adj, nullptr, stream)) != SWE_OK) return st;
-            res->n_adj_steps++;
-            src = dst;
+    // a 1D adjoint grid that fits one workgroup: the whole phase in one launch
+    if (!twod && !pb->launch_per_step && swe::run1d_lds_bytes(AG->nx)) {
+        swe::Run1dArgs ra;
+        std::memset(&ra, 0, sizeof ra);
+        ra.P = make_kparams(AG, P, AB, frame(0), frame(0), dt_adj, nullptr);
+        ra.frames = pb->frames;
+        ra.fplane = aplane;
+        ra.K = K;
+        ra.nsub = nsub;
+        HIP_TRY(swe::launch_adj_run1d(ra, s));
+        res->n_adj_steps = K * nsub;
+    } else {
+        for (int k = 1; k <= K; ++k) {
+            swe_fields src = frame(k - 1);
+            for (int sstep = 0; sstep < nsub; ++sstep) {
+                bool last = sstep == nsub - 1;
+                swe_fields dst = last ? frame(k) : ((sstep & 1) ? Bf : A);
+                if ((st = adj_step(AG, P, AB, src, dst, dt_adj, nullptr, stream)) != SWE_OK) return st;
+                res->n_adj_steps++;
+                src = dst;
+            }
         }
     }
 
@@ -676,6 +709,36 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
     fl.adj_grid = interp ? AG : nullptr;
     fl.adj_B = interp ? AB : nullptr;
     fl.bounds = bounds;
+    // a 1D forward grid that fits one workgroup: each round of attempts in one
+    // launch, its flagged states flagged afterwards in two
+    const bool run1d = !twod && w.hist && swe::run1d_lds_bytes(G->nx);
+    swe::Run1dArgs ra;
+    swe::FlagParams hf;
+    swe::HistArgs ha;
+    if (run1d) {
+        std::memset(&ra, 0, sizeof ra);
+        ra.P = make_kparams(G, P, pb->B, A, Bf, 1.0, nullptr);
+        ra.P.ctl = w.ctl;
+        ra.P.cfl_desired = P->cfl_desired;
+        ra.P.cfl_max = P->cfl_max;
+        ra.flag_every = pb->flag_every;
+        ra.hist = w.hist;
+        ra.hist_t = w.hist_t;
+        ra.hist_done = w.hist_done;
+        ra.n_rec = w.n_rec;
+        std::memset(&hf, 0, sizeof hf);
+        hf.nx = G->nx; hf.ny = 1; hf.pitch = G->pitch; hf.ncomp = 2;
+        hf.twod = 0; hf.nonlinear = 0;
+        hf.sea_level = P->sea_level; hf.dry_tol = P->dry_tol; hf.tol = pb->tol;
+        hf.B = pb->B; hf.frames = pb->frames;
+        hf.flag_acc = pb->flag_acc; hf.maxip_acc = pb->maxip_acc;
+        hf.bounds = bounds;
+        if (interp && (st = setup_interp(hf, G, AG, AB)) != SWE_OK) return st;
+        std::memset(&ha, 0, sizeof ha);
+        ha.hist = w.hist; ha.hist_t = w.hist_t; ha.hist_done = w.hist_done; ha.n_rec = w.n_rec;
+        ha.m = w.hist_m;
+        ha.t0 = pb->t0; ha.ts = pb->ts; ha.tf = pb->tf; ha.K = K;
+    }
     swe_ctl hc;
     for (int j = 1; j <= K; ++j) {
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;
@@ -695,7 +758,14 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
                             dt0);
             double need = std::ceil((tout - hc.s.t) / hc.s.dt);
             int n = (int)std::min(std::max(need, 0.0) + 2.0, 100000.0);
-            if ((st = swe_advance_flagged(G, P, pb->B, A, Bf, w.ctl, n, &fl, stream)) != SWE_OK) return st;
+            if (run1d) {
+                ra.max_attempts = std::min(n, swe::RUN1D_RECORDS);
+                ha.flags_final = fl.flags_final;
+                HIP_TRY(swe::launch_fwd_run1d(ra, s));
+                HIP_TRY(swe::launch_hist_flag(hf, ha, s));
+            } else if ((st = swe_advance_flagged(G, P, pb->B, A, Bf, w.ctl, n, &fl, stream)) != SWE_OK) {
+                return st;
+            }
             HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (hc.n_nonfinite) return fail(SWE_E_NONFINITE, "non-finite state near t = %g", hc.s.t);
@@ -708,7 +778,8 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
             if (!hc.s.done && (!(hc.s.dt >= 1e-6 * dt0) || stalled >= 3))
                 return fail(SWE_E_CFL, "time step collapsed at t = %g (dt = %g, initial %g)", hc.s.t, hc.s.dt,
                             dt0);
-            if (++rounds > 1000 || hc.s.n_rejected > 1000) return fail(SWE_E_CFL, "no progress at t = %g", hc.s.t);
+            if (++rounds > (run1d ? 400000 : 1000) || hc.s.n_rejected > 1000)
+                return fail(SWE_E_CFL, "no progress at t = %g", hc.s.t);
         }
         if (pb->surface_flags_at) {
             swe_fields now = hc.s.cur ? Bf : A;

@@ -4,11 +4,9 @@
 #include <stdint.h>
 
 #include "swe.h"
+#include "swe_device.h"
 
 namespace swe {
-
-struct KParams;
-struct LevelArgs;
 
 enum { MODEL_NL = 0, MODEL_LIN = 1, MODEL_ADJ = 2 };
 
@@ -44,6 +42,39 @@ struct FlagCtl {
     int8_t *flags_final;
 };
 
+// A one-dimensional phase marched in one workgroup (state in LDS).
+constexpr int RUN1D_THREADS = 1024;           // 16 wavefronts
+constexpr int RUN1D_WAVES = RUN1D_THREADS / 64;
+constexpr int RUN1D_MAXS = 4;                 // strips of 60 cells per wavefront
+constexpr int RUN1D_MAX_NX = RUN1D_WAVES * RUN1D_MAXS * 60;
+constexpr int RUN1D_RECORDS = 256;            // flagged states kept per launch
+
+struct Run1dArgs {
+    KParams P;                 // grid, model, bottom; in* = plane set a, out* = plane set b
+    // adjoint (fixed dt = P.dt): snapshot k = state after k*nsub steps from snapshot 0
+    double *frames;            //   snapshot k, component c at frames + (2k + c)*fplane
+    size_t fplane;
+    int K, nsub;
+    // forward under device-side control (P.ctl): up to max_attempts attempts;
+    // the states that are to be flagged are recorded (two planes of nx each),
+    // with their time and whether they end the segment
+    int max_attempts, flag_every;
+    double *hist, *hist_t;
+    int *hist_done, *n_rec;
+};
+
+// Flagging of the recorded states of a 1D forward launch: m per record and
+// cell (in order of the records), then the records folded into the outputs
+// one after the other, as the per-attempt flag passes would.
+struct HistArgs {
+    const double *hist, *hist_t;
+    const int *hist_done, *n_rec;
+    double *m;
+    double t0, ts, tf;
+    int K;
+    int8_t *flags_final;
+};
+
 struct CellParams {
     int nx, ny, pitch;
     double dx, dy, x_lo, y_lo;
@@ -73,6 +104,11 @@ hipError_t launch_flag_ctl(const FlagParams &F, const FlagCtl &C, hipStream_t s)
 hipError_t launch_level_step(const KParams &P, const LevelArgs &L, hipStream_t s);
 hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s);
 int level_persistent_capacity();
+// LDS bytes of a 1D run over nx cells, or 0 where it does not fit one workgroup
+size_t run1d_lds_bytes(int nx);
+hipError_t launch_adj_run1d(const Run1dArgs &A, hipStream_t s);
+hipError_t launch_fwd_run1d(const Run1dArgs &A, hipStream_t s);
+hipError_t launch_hist_flag(const FlagParams &F, const HistArgs &H, hipStream_t s);
 hipError_t launch_count_diff(const double *a, const double *b, long long n, int *out, hipStream_t s);
 hipError_t launch_ctl_set(swe_ctl *c, double t, double dt, double t_out, int cur, hipStream_t s);
 hipError_t launch_ctl_retarget(swe_ctl *c, double t_out, hipStream_t s);

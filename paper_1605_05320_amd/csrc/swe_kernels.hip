@@ -595,18 +595,17 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
     }
 }
 
-// One row (ny == 1): the x-sweep of the marching step without y-terms.
+// One row (ny == 1): the x-sweep of the marching step without y-terms, on
+// the lanes of one strip (lane l holds cell i = strip*STRIP + l - HALO, whose
+// data is c).  Writes the strip's cells to o0, o1 and returns the lane's
+// contribution to the Courant number; counts non-finite results in nbad.
 template <class M>
-__global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
+__device__ __forceinline__ double step1d_lanes(const KParams &P, const typename M::Cell &c, int lane, int i,
+                                               double nu, double *o0, double *o1, int &nbad)
 {
-    if (!resolve_ctl(P)) return;
-    const int lane = threadIdx.x;
-    const int i = blockIdx.x * STRIP + lane - HALO;
-    const double nu = P.dt / P.dx;
     const bool core = lane >= HALO && lane < WAVE - HALO && i < P.nx;
     const bool xedge_in = lane >= HALO && lane <= WAVE - HALO && i <= P.nx;
     using Cell = typename M::Cell;
-    Cell c = M::load(P, uniform_geo(P), i, 0);
     Cell l = M::lo_cell(c);
     Edge x;
     M::solve(l, c, false, P, x);
@@ -619,7 +618,6 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
     double FE[3], amE[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) { FE[k] = from_hi(F[k]); amE[k] = from_hi(x.am[k]); }
-    int nbad = 0;
     if (core) {
         double o[2];
 #pragma unroll
@@ -632,14 +630,230 @@ __global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
             o[k] = qv;
         }
         if (!isfinite(o[0]) || !isfinite(o[1])) ++nbad;
-        P.out0[i] = o[0];
-        P.out1[i] = o[1];
+        o0[i] = o[0];
+        o1[i] = o[1];
     }
     double cfl = 0.0;
     if (xedge_in)
 #pragma unroll
         for (int p = 0; p < M::NW; ++p) cfl = dmax(cfl, nu * fabs(x.s[p]));
+    return cfl;
+}
+
+template <class M>
+__global__ void __launch_bounds__(WAVE) k_step1d(KParams P)
+{
+    if (!resolve_ctl(P)) return;
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x * STRIP + lane - HALO;
+    const double nu = P.dt / P.dx;
+    int nbad = 0;
+    const double cfl = step1d_lanes<M>(P, M::load(P, uniform_geo(P), i, 0), lane, i, nu, P.out0, P.out1, nbad);
     march_epilogue(P, lane, cfl, 0, nbad);
+}
+
+// ---------------------------------------------------------------------------
+// A one-dimensional phase in one workgroup.  A 1D grid of a few thousand
+// cells cannot fill the chip, and with one launch per step (and one per flag
+// pass) its run is bound by launch latency.  Here one workgroup keeps the
+// state in LDS (two buffers) and marches every step of the phase: its
+// wavefronts take the strips of k_step1d round-robin (same lanes and halos,
+// the same arithmetic through step1d_lanes) and meet at one barrier per step.
+// The linear models' cell coefficients depend on the bottom only and are
+// computed once per lane.
+// ---------------------------------------------------------------------------
+struct Strip1d {
+    int mi, neg;        // mapped cell index of the lane; wall ghost (normal momentum negated)
+    double c, gh;       // static part of the linear cell
+    int wet;
+};
+
+template <class M>
+__device__ __forceinline__ void strip1d_init(const KParams &P, int strip, int lane, Strip1d &st)
+{
+    const Geo G = uniform_geo(P);
+    const int i = strip * STRIP + lane - HALO;
+    RawCell r;
+    st.mi = map_index(i, G.nx, (G.bcm & 1) ? BC_EXTRAP : BC_WALL, (G.bcm & 2) ? BC_EXTRAP : BC_WALL, r.nxg);
+    r.nyg = false;
+    r.q0 = 0.0;
+    r.q1 = 0.0;
+    r.q2 = 0.0;
+    r.B = P.B[st.mi];
+    const LinCell c = M::cell(P, r);
+    st.neg = r.nxg;
+    st.c = c.c;
+    st.gh = c.gh;
+    st.wet = c.wet;
+}
+
+// the cell of lane `lane` from the state planes q0, q1 (the values lin_cell
+// gives for the raw cell)
+__device__ __forceinline__ LinCell strip1d_cell(const Strip1d &st, const double *q0, const double *q1)
+{
+    LinCell c;
+    c.q0 = q0[st.mi];
+    const double m = q1[st.mi];
+    c.q1 = st.neg ? -m : m;
+    c.q2 = 0.0;
+    c.c = st.c;
+    c.gh = st.gh;
+    c.wet = st.wet;
+    return c;
+}
+
+// Adjoint phase: snapshot 0 is given; snapshot k is the state after nsub
+// steps of dt = P.dt from snapshot k - 1.
+template <class M>
+__global__ void __launch_bounds__(RUN1D_THREADS) k_adj_run1d(Run1dArgs A)
+{
+    extern __shared__ double lds[];
+    const int nx = A.P.nx;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1), nwaves = blockDim.x / WAVE;
+    const int nstrips = (nx + STRIP - 1) / STRIP;
+    double *q[2][2] = {{lds, lds + nx}, {lds + 2 * nx, lds + 3 * nx}};
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+        q[0][0][k] = A.frames[k];
+        q[0][1][k] = A.frames[A.fplane + k];
+    }
+    Strip1d st[RUN1D_MAXS];
+#pragma unroll
+    for (int s = 0; s < RUN1D_MAXS; ++s) {
+        const int strip = wave + s * nwaves;
+        if (strip < nstrips) strip1d_init<M>(A.P, strip, lane, st[s]);
+    }
+    __syncthreads();
+    const double nu = A.P.dt / A.P.dx;
+    int cur = 0;
+    for (int k = 1; k <= A.K; ++k) {
+        for (int sub = 0; sub < A.nsub; ++sub) {
+#pragma unroll
+            for (int s = 0; s < RUN1D_MAXS; ++s) {
+                const int strip = wave + s * nwaves;
+                if (strip >= nstrips) break;
+                int nbad = 0;
+                (void)step1d_lanes<M>(A.P, strip1d_cell(st[s], q[cur][0], q[cur][1]), lane,
+                                      strip * STRIP + lane - HALO, nu, q[cur ^ 1][0], q[cur ^ 1][1], nbad);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
+        // the next step writes the other buffer; the one after waits at a
+        // barrier that every thread reaches only after its copy
+        double *f = A.frames + (size_t)2 * k * A.fplane;
+        for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+            f[i] = q[cur][0][i];
+            f[A.fplane + i] = q[cur][1][i];
+        }
+    }
+}
+
+// Forward phase under device-side control: the attempts of swe_advance with
+// flagging, the control rule applied by every thread to the attempt's
+// Courant number (the maximum of the lanes' values as bit patterns; equal to
+// the per-step launches' for every finite state, whose run fails either way
+// when a value is NaN).  The states that are to be flagged are recorded for
+// k_hist_flag.  At the end the control block holds what the per-step launches
+// and k_ctl_finish leave there.
+template <class M>
+__global__ void __launch_bounds__(RUN1D_THREADS) k_fwd_run1d(Run1dArgs A)
+{
+    extern __shared__ double lds[];
+    const int nx = A.P.nx;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1), nwaves = blockDim.x / WAVE;
+    const int nstrips = (nx + STRIP - 1) / STRIP;
+    double *q[2][2] = {{lds, lds + nx}, {lds + 2 * nx, lds + 3 * nx}};
+    unsigned long long *red = (unsigned long long *)(lds + 4 * nx);   // [2][RUN1D_WAVES]
+    int *redn = (int *)(red + 2 * RUN1D_WAVES);                        // [2][RUN1D_WAVES]
+    swe_ctl *c = A.P.ctl;
+    swe_ctl_state S = c->s;
+    const double *g0 = S.cur ? A.P.out0 : A.P.in0, *g1 = S.cur ? A.P.out1 : A.P.in1;
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+        q[0][0][k] = g0[k];
+        q[0][1][k] = g1[k];
+    }
+    Strip1d st[RUN1D_MAXS];
+#pragma unroll
+    for (int s = 0; s < RUN1D_MAXS; ++s) {
+        const int strip = wave + s * nwaves;
+        if (strip < nstrips) strip1d_init<M>(A.P, strip, lane, st[s]);
+    }
+    __syncthreads();
+    int cur = 0, nrec = 0, nbad_acc = 0, a = 0;
+    unsigned long long last_bits = 0;
+    for (; a < A.max_attempts && !S.done; ++a) {
+        const double nu = S.dt / A.P.dx;
+        unsigned long long bits = 0;
+        int nbad = 0;
+#pragma unroll
+        for (int s = 0; s < RUN1D_MAXS; ++s) {
+            const int strip = wave + s * nwaves;
+            if (strip >= nstrips) break;
+            const double cf = step1d_lanes<M>(A.P, strip1d_cell(st[s], q[cur][0], q[cur][1]), lane,
+                                              strip * STRIP + lane - HALO, nu, q[cur ^ 1][0], q[cur ^ 1][1], nbad);
+            const unsigned long long b = (unsigned long long)__double_as_longlong(cf);
+            bits = b > bits ? b : bits;
+        }
+        bits = wave_max_u64(bits);
+        if (__any(nbad > 0)) nbad = wave_sum(nbad);
+        if (lane == 0) {
+            // (the launch has RUN1D_WAVES wavefronts: every slot is written)
+            red[(a & 1) * RUN1D_WAVES + wave] = bits;
+            redn[(a & 1) * RUN1D_WAVES + wave] = nbad;
+        }
+        __syncthreads();
+        // the slots of this attempt are read before the next barrier; the
+        // next attempt writes the other half
+        unsigned long long all = 0;
+        int nball = 0;
+#pragma unroll
+        for (int w = 0; w < RUN1D_WAVES; ++w) {
+            const unsigned long long v = red[(a & 1) * RUN1D_WAVES + w];
+            all = v > all ? v : all;
+            nball += redn[(a & 1) * RUN1D_WAVES + w];
+        }
+        S = ctl_apply(S, __longlong_as_double((long long)all), A.P.cfl_desired, A.P.cfl_max);
+        last_bits = all;
+        if (S.last_accepted) {
+            cur ^= 1;
+            nbad_acc += nball;
+            if (A.hist && (S.done || S.n_accepted % A.flag_every == 0)) {
+                double *h = A.hist + (size_t)nrec * 2 * nx;
+                for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+                    h[k] = q[cur][0][k];
+                    h[nx + k] = q[cur][1][k];
+                }
+                if (threadIdx.x == 0) {
+                    A.hist_t[nrec] = S.t;
+                    A.hist_done[nrec] = S.done;
+                }
+                ++nrec;
+            }
+        }
+    }
+    const bool any = A.max_attempts > 0;
+    if (any && a < A.max_attempts) {
+        // attempts left after the segment ended run as skipped launches: the
+        // last of them resolves with Courant number 0 (accepted flag cleared)
+        S = ctl_apply(S, 0.0, A.P.cfl_desired, A.P.cfl_max);
+        last_bits = 0;
+    }
+    double *o0 = S.cur ? A.P.out0 : const_cast<double *>(A.P.in0);
+    double *o1 = S.cur ? A.P.out1 : const_cast<double *>(A.P.in1);
+    for (int k = threadIdx.x; k < nx; k += blockDim.x) {
+        o0[k] = q[cur][0][k];
+        o1[k] = q[cur][1][k];
+    }
+    if (threadIdx.x == 0) {
+        if (any) {
+            c->s = S;
+            c->cfl_bits = last_bits;
+            if (nbad_acc) c->n_nonfinite = c->n_nonfinite + nbad_acc;
+            if (nrec) c->n_flag_calls = c->n_flag_calls + nrec;
+            clear_ring(c);
+        }
+        *A.n_rec = nrec;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -999,6 +1213,59 @@ __global__ void __launch_bounds__(256) k_flag_ctl(FlagParams F, FlagCtl C)
     }
 }
 
+// The recorded states of a 1D forward launch: m of record blockIdx.y at every
+// cell (window from the record's time, as k_flag_ctl takes it) ...
+template <bool INTERP>
+__global__ void __launch_bounds__(256) k_hist_flag(FlagParams F, HistArgs H)
+{
+    const int r = blockIdx.y;
+    if (r >= *H.n_rec) return;
+    int lo, hi;
+    dev_window(H.hist_t[r], H.t0, H.ts, H.tf, H.K, lo, hi);
+    F.k_lo = lo;
+    F.k_hi = hi;
+    F.q0 = H.hist + (size_t)r * 2 * F.nx;
+    F.q1 = F.q0 + F.nx;
+    F.q2 = nullptr;
+    const long long n = F.nx;
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (long long wb = (long long)blockIdx.x * blockDim.x + (threadIdx.x - lane); wb < n;
+         wb += (long long)gridDim.x * blockDim.x) {
+        const bool live = wb + lane < n;
+        const int i = (int)(live ? wb + lane : wb);
+        const double m = flag_m<false, INTERP>(F, i, 0, (size_t)i, live, F.bounds ? wave_rect(F, wb, n) : IdxRect{0, 0, 0, 0});
+        if (live) H.m[(size_t)r * F.nx + i] = m;
+    }
+}
+
+// ... then per cell the records in order: flags of the record that ends the
+// segment, the running OR of the flags and maximum of m.
+__global__ void __launch_bounds__(256) k_hist_fold(FlagParams F, HistArgs H)
+{
+    const int nrec = *H.n_rec;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < F.nx; i += gridDim.x * blockDim.x) {
+        int8_t acc = F.flag_acc ? F.flag_acc[i] : 0;
+        double macc = F.maxip_acc ? F.maxip_acc[i] : 0.0;
+        for (int r0 = 0; r0 < nrec; r0 += 8) {
+            // eight records' loads in flight together, folded in order
+            double mv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) mv[u] = r0 + u < nrec ? H.m[(size_t)(r0 + u) * F.nx + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (r0 + u >= nrec) break;
+                const double m = mv[u];
+                const int8_t fl = m > F.tol ? 1 : 0;
+                if (H.hist_done[r0 + u] && H.flags_final) H.flags_final[i] = fl;
+                acc = (int8_t)(acc | fl);
+                macc = dmax(macc, m);
+            }
+        }
+        if (F.flag_acc) F.flag_acc[i] = acc;
+        if (F.maxip_acc) F.maxip_acc[i] = macc;
+    }
+}
+
 // Target data, initial state, maximum speed: per-cell helpers.
 __global__ void __launch_bounds__(256) k_target(CellParams C, double xc, double yc, double R, int shape)
 {
@@ -1221,6 +1488,56 @@ hipError_t launch_flag(const FlagParams &F, hipStream_t s)
     case 2: hipLaunchKernelGGL((k_flag<true, false>), grid, dim3(256), 0, s, F); break;
     default: hipLaunchKernelGGL((k_flag<true, true>), grid, dim3(256), 0, s, F); break;
     }
+    return hipGetLastError();
+}
+
+size_t run1d_lds_bytes(int nx)
+{
+    if (nx < 2 || nx > RUN1D_MAX_NX) return 0;
+    const size_t bytes = (size_t)4 * nx * sizeof(double) + 2 * RUN1D_WAVES * (sizeof(unsigned long long) + sizeof(int));
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    if (bytes > (size_t)lim) return 0;
+    if (bytes > 65536) {
+        // beyond 64 KiB the kernels must be allowed the larger allocation;
+        // where that is refused the step-by-step launches are used instead
+        if (hipFuncSetAttribute((const void *)k_adj_run1d<ADJ<false>>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes) != hipSuccess ||
+            hipFuncSetAttribute((const void *)k_fwd_run1d<LIN1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+    }
+    return bytes;
+}
+
+hipError_t launch_adj_run1d(const Run1dArgs &A, hipStream_t s)
+{
+    const size_t lds = run1d_lds_bytes(A.P.nx);
+    if (!lds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_run1d<ADJ<false>>, dim3(1), dim3(RUN1D_THREADS), lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_run1d(const Run1dArgs &A, hipStream_t s)
+{
+    const size_t lds = run1d_lds_bytes(A.P.nx);
+    if (!lds || A.max_attempts > RUN1D_RECORDS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fwd_run1d<LIN1>, dim3(1), dim3(RUN1D_THREADS), lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist_flag(const FlagParams &F, const HistArgs &H, hipStream_t s)
+{
+    const unsigned bx = (unsigned)((F.nx + 255) / 256);
+    const dim3 grid(bx, RUN1D_RECORDS);
+    if (F.interp) hipLaunchKernelGGL((k_hist_flag<true>), grid, dim3(256), 0, s, F, H);
+    else hipLaunchKernelGGL((k_hist_flag<false>), grid, dim3(256), 0, s, F, H);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hist_fold, dim3(bx), dim3(256), 0, s, F, H);
     return hipGetLastError();
 }
 

@@ -52,7 +52,8 @@ class swe_problem(C.Structure):
                 ("frames", C.c_void_p), ("q_out", swe_fields), ("flags_at", C.c_void_p),
                 ("flag_acc", C.c_void_p), ("maxip_acc", C.c_void_p),
                 ("surface_tol", C.c_double), ("surface_flags_at", C.c_void_p),
-                ("adj_grid", swe_grid), ("adj_B", C.c_void_p)]
+                ("adj_grid", swe_grid), ("adj_B", C.c_void_p),
+                ("launch_per_step", C.c_int32), ("reserved", C.c_int32)]
 
 
 class swe_result(C.Structure):
@@ -241,9 +242,10 @@ def swe_surface_flag(grid: Grid, prm: Params, B, q, tol, flags=None, flag_acc=No
 def make_problem(grid: Grid, prm: Params, B, eta0, target, t0, ts, tf, K, tol, frames, q_out,
                  flags_at=None, flag_acc=None, maxip_acc=None, flag_every=1, shape=GAUSS,
                  surface_tol=0.0, surface_flags_at=None, adj_grid: Grid = None, adj_B=None,
-                 full_frames=0) -> swe_problem:
+                 full_frames=0, launch_per_step=0) -> swe_problem:
     pb = swe_problem()
     pb.full_frames = full_frames
+    pb.launch_per_step = launch_per_step
     pb.grid = grid.c()
     pb.params = prm.c()
     pb.B, pb.eta0 = B.data_ptr(), eta0.data_ptr()
