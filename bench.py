@@ -155,7 +155,8 @@ def main():
     ap.add_argument("--adj-only", type=int, default=0, metavar="K",
                     help="run the 1024^2 adjoint step K times and exit (profiler runs)")
     ap.add_argument("--flag-only", type=int, default=0, metavar="K",
-                    help="run the 512^2 flag pass (34-snapshot window) K times and exit (profiler runs)")
+                    help="run the --flag-n flag pass (34-snapshot window) K times and exit (profiler runs)")
+    ap.add_argument("--flag-n", type=int, default=512, help="grid side of the --flag-only pass")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
                     help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -200,7 +201,7 @@ def main():
         print(json.dumps({"adj_launches": args.adj_only}), flush=True)
         return
     if args.flag_only > 0:
-        flag, _, _ = flag_pass_512(S, torch, I, np, f64)
+        flag, _, _ = flag_pass(S, torch, I, np, f64, n=args.flag_n)
         for _ in range(args.flag_only):
             flag()
         if args.copy_probe:
@@ -359,12 +360,11 @@ def busy_state(S, torch, I, np, f64, n):
 FLAG_BYTES_PER_CELL_W34 = 32 + 24 * 34 + 1 + 1 + 1 + 16   # q, B, 34 snapshots, flag, accumulators
 
 
-def flag_pass_512(S, torch, I, np, f64):
-    """The flag pass at 512^2 with a 34-snapshot window (the widest window of
+def flag_pass(S, torch, I, np, f64, n=512):
+    """The flag pass at n^2 with a 34-snapshot window (the widest window of
     the adjoint-flagging workload: snapshots 30..63 of 64), with the running
     flag and max-inner-product accumulators; returns the call and its
     algorithmic bytes."""
-    n = 512
     b = I.basin(n, 3)
     g = S.Grid(n, n, b.grid.dx, b.grid.dy)
     p = S.Params()
@@ -409,7 +409,7 @@ def secondary(S, torch, I, np, f64):
     t = _time_events(torch, adj_step_1024(S, torch, I, f64), 200)
     out["adj_step_1024_cell_updates_per_s"] = n * n / t
     out["adj_step_1024_us"] = t * 1e6
-    flag, fbytes, ctx = flag_pass_512(S, torch, I, np, f64)
+    flag, fbytes, ctx = flag_pass(S, torch, I, np, f64)
     t = _time_events(torch, flag, 100)
     n = 512
     g, p, B, q, K, fl, acc, macc = (ctx[k] for k in ("g", "p", "B", "q", "K", "fl", "acc", "macc"))
@@ -417,20 +417,11 @@ def secondary(S, torch, I, np, f64):
     out["flag_512_w34_GBs"] = fbytes / t / 1e9
     # the same window at 1024^2: 34 snapshots of 25 MB, 855 MB in all, more
     # than the 256 MB last-level cache holds, so every pass streams from HBM
-    n1 = 1024
-    b1 = I.basin(n1, 3)
-    g1 = S.Grid(n1, n1, b1.grid.dx, b1.grid.dy)
-    B1 = torch.tensor(b1.B, **f64)
-    fr1 = torch.randn(K + 1, 3, n1, n1, **f64) * 1e-3
-    q1 = [torch.tensor(np.maximum(0.0, -b1.B), **f64), torch.zeros(n1, n1, **f64), torch.zeros(n1, n1, **f64)]
-    fl1 = torch.empty(n1, n1, dtype=torch.int8, device=B.device)
-    acc1 = torch.zeros(n1, n1, dtype=torch.int8, device=B.device)
-    macc1 = torch.zeros(n1, n1, **f64)
-    t = min(_time_events(torch, lambda: S.adj_flag(g1, p, B1, q1, fr1, K, 30, 63, 1e-4, fl1, None, acc1, macc1),
-                         10) for _ in range(3))
+    flag1, fbytes1, _ = flag_pass(S, torch, I, np, f64, n=1024)
+    t = min(_time_events(torch, flag1, 10) for _ in range(3))
     out["flag_1024_w34_us"] = t * 1e6
-    out["flag_1024_w34_GBs"] = n1 * n1 * FLAG_BYTES_PER_CELL_W34 / t / 1e9
-    del fr1, q1, B1, fl1, acc1, macc1
+    out["flag_1024_w34_GBs"] = fbytes1 / t / 1e9
+    del flag1
     torch.cuda.empty_cache()
     # the same pass with the snapshots on a 256^2 adjoint grid (bilinear
     # interpolation at every cell and snapshot)
