@@ -1119,11 +1119,31 @@ __global__ void __launch_bounds__(256) k_frame_bounds(const double *frames, int 
         jlo = min(jlo, __shfl_xor(jlo, off, WAVE));
         jhi = max(jhi, __shfl_xor(jhi, off, WAVE));
     }
-    if ((threadIdx.x & (WAVE - 1)) == 0 && ihi >= 0) {
-        atomicMin(&bounds[4 * k + 0], ilo);
-        atomicMax(&bounds[4 * k + 1], ihi);
-        atomicMin(&bounds[4 * k + 2], jlo);
-        atomicMax(&bounds[4 * k + 3], jhi);
+    // the workgroup's four wavefronts meet in LDS, then one thread updates
+    // the snapshot's box (one set of atomics per workgroup: the workgroups of
+    // a snapshot all update the same four words)
+    __shared__ int box[4][4];
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        box[w][0] = ilo;
+        box[w][1] = ihi;
+        box[w][2] = jlo;
+        box[w][3] = jhi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < (int)(blockDim.x / WAVE); ++v) {
+            ilo = min(ilo, box[v][0]);
+            ihi = max(ihi, box[v][1]);
+            jlo = min(jlo, box[v][2]);
+            jhi = max(jhi, box[v][3]);
+        }
+        if (ihi >= 0) {
+            atomicMin(&bounds[4 * k + 0], ilo);
+            atomicMax(&bounds[4 * k + 1], ihi);
+            atomicMin(&bounds[4 * k + 2], jlo);
+            atomicMax(&bounds[4 * k + 3], jhi);
+        }
     }
 }
 
@@ -1473,7 +1493,7 @@ hipError_t launch_frame_bounds(const double *frames, int nx, int ny, int pitch, 
     const int nf = K + 1;
     hipLaunchKernelGGL(k_bounds_init, dim3((4 * nf + 255) / 256), dim3(256), 0, s, bounds, nf, nx, ny);
     long long blocks = ((long long)nx * ny + 255) / 256;
-    if (blocks > 256) blocks = 256;
+    if (blocks > 64) blocks = 64;
     hipLaunchKernelGGL(k_frame_bounds, dim3((unsigned)blocks, (unsigned)nf), dim3(256), 0, s, frames, nx, ny, pitch,
                        ncomp, bounds);
     return hipGetLastError();
