@@ -32,8 +32,9 @@ METRIC = "cell-updates/s FP64 2D SWE step (% HBM roofline); batched/served scen/
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("swe_device.h", "swe_kernels.hip"):
-        with open(os.path.join(ROOT, "paper_1605_05320_amd", "csrc", f), "rb") as fh:
+    for f in ("paper_1605_05320_amd/csrc/swe_device.h", "paper_1605_05320_amd/csrc/swe_kernels.hip",
+              "include/swe.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

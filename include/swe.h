@@ -218,7 +218,7 @@ SWE_API swe_status adj_frame_bounds(const swe_grid *grid, const double *frames, 
  * attempt costs exactly one kernel launch; swe_advance ends with one small
  * kernel that resolves the last attempt into ctl->s.
  */
-#define SWE_CTL_SPREAD 32
+#define SWE_CTL_SPREAD 8
 
 typedef struct {
     double t;               /* time of the current state */
@@ -242,8 +242,9 @@ typedef struct {
     /* kernel-internal: Courant numbers of the running attempts, attempt k's
      * being the largest of ring[k][j][0] over j < SWE_CTL_SPREAD: the
      * wavefronts of a launch spread their atomic maxima over these words, one
-     * 128-byte line each (atomics on one word are serialised, which made a
-     * single word cost microseconds per launch); words 1 and 2 of each line
+     * 128-byte line each (atomics on one word are serialised, and every
+     * wavefront of the next attempt reads all of them: 8 words balance the
+     * two); words 1 and 2 of each line
      * collect the attempt's clamped and non-finite cells, which are added to
      * n_clamped and n_nonfinite once the attempt is known to be accepted */
     uint64_t ring[3][SWE_CTL_SPREAD][16];

@@ -62,7 +62,7 @@ class swe_result(C.Structure):
                 ("dt_adj", C.c_double), ("t_end", C.c_double)]
 
 
-CTL_SPREAD = 32     # SWE_CTL_SPREAD
+CTL_SPREAD = 8      # SWE_CTL_SPREAD
 
 
 class swe_ctl_state(C.Structure):
