@@ -182,8 +182,9 @@ SWE_API swe_status adj_window(double t, double t0, double ts, double tf, int32_t
  * An empty window (k_lo > k_hi) gives m = 0.  flags (int8 plane) and the
  * optional maxip, flag_acc (|= flag), maxip_acc (= max(., m)) planes use the
  * grid's pitch.  bounds (device, nullable): the snapshots' non-zero boxes of
- * adj_frame_bounds; a snapshot whose box excludes a cell is not read for that
- * cell (its inner product there is |0| = 0: the same m, less traffic).
+ * adj_frame_bounds; a snapshot whose box misses every cell of a group of 64
+ * consecutive cells is not read for that group (its inner product there is
+ * |0| = 0: the same m for a finite state, less traffic).
  */
 SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const double *B,
                     swe_fields q, const double *frames, int32_t K, int32_t k_lo,
@@ -196,8 +197,10 @@ SWE_API swe_status adj_flag(const swe_grid *grid, const swe_params *prm, const d
  * value in any plane (a NaN counts as non-zero): bounds[4k..4k+3] =
  * (i_lo, i_hi, j_lo, j_hi), inclusive; (nx, -1, ny, -1) for a snapshot that is
  * zero everywhere.  The adjoint is exactly zero outside the domain of
- * dependence of the target (Sec. 4), so early snapshots have small boxes.
- * bounds: device, 4*(K+1) int32.  Enqueue only.
+ * dependence of the target (Sec. 4), so with a target of compact support
+ * (the disk of Sec. 6) the snapshots near t_f have small boxes.  bounds:
+ * device, 4*(K+1) int32, owned by the caller.  Enqueue only.  SWE_E_INVAL:
+ * a bad grid, null frames or bounds, K < 0.
  */
 SWE_API swe_status adj_frame_bounds(const swe_grid *grid, const double *frames, int32_t K, int32_t *bounds,
                                     void *stream);
@@ -555,8 +558,9 @@ typedef struct {
     double t0, ts, tf;      /* run [t0, tf]; target time range [ts, tf] */
     double tol;             /* flagging tolerance */
     int32_t flag_every;     /* flag after every flag_every accepted steps (>= 1) */
-    int32_t full_frames;    /* 0: the flag passes skip, per cell, the snapshots that are exactly zero
-                               there (adj_frame_bounds); 1: they read every snapshot in full (same results) */
+    int32_t full_frames;    /* 0: the flag passes skip the snapshots that are exactly zero over a
+                               group of cells (adj_frame_bounds); 1: they read every snapshot in full
+                               (same results for finite states) */
     double *frames;         /* device, (K+1)*ncomp*ny*pitch doubles of the adjoint grid (output) */
     swe_fields q_out;       /* device, final forward state (output) */
     int8_t *flags_at;       /* device, (K+1)*ny*pitch: flags at t0 + j ds; nullable */
@@ -572,7 +576,9 @@ typedef struct {
     int32_t launch_per_step; /* 1D problems: 0 runs each phase of a grid of up to 3840 cells in one
                                 workgroup (state in LDS, one launch per phase, the flagged states
                                 recorded and flagged afterwards); 1 launches every step and flag
-                                pass as for 2D grids (same results bit for bit).  2D: ignored. */
+                                pass as for 2D grids (same results bit for bit for finite states;
+                                the workgroup needs 32 B of LDS per cell, and a grid that does not
+                                fit runs step by step either way).  2D: ignored. */
     int32_t reserved;
 } swe_problem;
 
