@@ -61,3 +61,36 @@ def test_static_workspace_matches_swe_run(S, sizes):
         for x, y in zip(got, ref):
             assert np.array_equal(x, y, equal_nan=False)
         assert ref[-2].any(), "some cell must be flagged"
+
+
+def problem1d(S, n, seed, K=12, tf=3600.0, tol=1e-3):
+    s = I.shelf1d(n, seed=seed)
+    g = S.Grid(n, 1, s.dx, 1.0, s.x_lo)
+    out = {
+        "frames": torch.full((K + 1, 2, 1, n), float("nan"), dtype=torch.float64, device=DEV),
+        "q": [torch.full((1, n), float("nan"), dtype=torch.float64, device=DEV) for _ in range(2)],
+        "flags_at": torch.full((K + 1, 1, n), 7, dtype=torch.int8, device=DEV),
+        "acc": torch.zeros(1, n, dtype=torch.int8, device=DEV),
+        "macc": torch.zeros(1, n, dtype=torch.float64, device=DEV),
+    }
+    pb = S.make_problem(g, S.Params(model=S.LINEAR), dev(s.B.reshape(1, n)), dev(s.eta0.reshape(1, n)), s.target,
+                        0.0, 0.0, tf, K, tol, out["frames"], out["q"], out["flags_at"], out["acc"], out["macc"])
+    return pb, out
+
+
+@pytest.mark.parametrize("sizes", [((2000, 0), (1000, 1))])
+def test_static_workspace_matches_swe_run_1d(S, sizes):
+    """The same for 1D runs, whose phases run in one workgroup with their
+    recorded states in the workspace."""
+    for n, seed in sizes:
+        print(f"swe_run_static: 1D {n} cells seed {seed}", flush=True)
+        pb, out = problem1d(S, n, seed)
+        assert S.swe_run_workspace_bytes(pb) <= S.STATIC_WORKSPACE_BYTES
+        ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, dtype=torch.float64, device=DEV)
+        ref, rcount = results(out, S.swe_run(pb, ws))
+        pb2, out2 = problem1d(S, n, seed)
+        got, gcount = results(out2, S.swe_run_static(pb2))
+        assert gcount == rcount
+        for x, y in zip(got, ref):
+            assert np.array_equal(x, y, equal_nan=False)
+        assert ref[-2].any(), "some cell must be flagged"
