@@ -864,6 +864,9 @@ def serve_bench(S, torch, I, np, n_req, nmin, nmax, K=32, ts=3600.0, tf=7200.0, 
     cells = [a.n * a.n for a in trace]
     steps = [s["n_adj_steps"] + s["n_fwd_steps"] for s in st_seq]
     return {
+        "trace": ("full: 256 requests, sides 256..2048" if (n_req, nmin, nmax) == (256, 256, 2048) else
+                  f"reduced: {n_req} requests, sides {nmin}..{nmax} (the full trace of 256 requests, sides "
+                  "256..2048, runs with --serve-full: about 5 minutes)"),
         "requests": n_req, "grid_side": [nmin, nmax], "snapshots": K, "t_final_s": tf, "window_start_s": ts,
         "tol": tol, "flag_every": flag_every, "max_active": max_active,
         "arena_GiB": round(arena_bytes / 2**30, 2), "footprint_GiB_max": round(max(foot) / 2**30, 3),
