@@ -2,6 +2,7 @@
 // piecewise-constant injection of the coarse state into refined patches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -16,16 +17,46 @@ struct Box {
     int i, j, nx, ny;
 };
 
+// The flagged cells are listed once; a box's recursion then works on the
+// part of the list inside it (the list is partitioned at every cut), so each
+// level of the recursion costs the number of flagged cells, not the area of
+// the boxes.  Shrinking, counting and the signatures see exactly the flagged
+// cells of the box, as a scan of its area would.
 class Clusterer {
 public:
-    Clusterer(const int8_t *f, int pitch, double eff, int min_side, int max_side)
-        : f_(f), pitch_(pitch), eff_(eff), min_(min_side), max_(max_side) {}
-
-    void run(Box b, std::vector<Box> &out)
+    Clusterer(const int8_t *f, int nx, int ny, int pitch, double eff, int min_side, int max_side)
+        : eff_(eff), min_(min_side), max_(max_side)
     {
-        if (!shrink(b)) return;
-        long long nflag = count(b);
-        long long area = (long long)b.nx * b.ny;
+        // eight cells at a time: flags are sparse, and a word of zeros is skipped whole
+        for (int j = 0; j < ny; ++j) {
+            const int8_t *row = f + (size_t)j * pitch;
+            int i = 0;
+            for (; i + 8 <= nx; i += 8) {
+                uint64_t w;
+                std::memcpy(&w, row + i, sizeof w);
+                if (w == 0) continue;
+                for (int k = 0; k < 8; ++k)
+                    if (row[i + k] != 0) pts_.push_back(Pt{i + k, j});
+            }
+            for (; i < nx; ++i)
+                if (row[i] != 0) pts_.push_back(Pt{i, j});
+        }
+    }
+
+    void run(std::vector<Box> &out) { run(0, pts_.size(), out); }
+
+private:
+    struct Pt {
+        int i, j;
+    };
+
+    // the flagged cells pts_[p0..p1) (all of them inside the box being split)
+    void run(size_t p0, size_t p1, std::vector<Box> &out)
+    {
+        if (p0 == p1) return;
+        const Box b = bounding_box(p0, p1);
+        const long long nflag = (long long)(p1 - p0);
+        const long long area = (long long)b.nx * b.ny;
         const bool efficient = (double)nflag >= eff_ * (double)area;
         if (efficient && b.nx <= max_ && b.ny <= max_) {
             out.push_back(b);
@@ -35,67 +66,44 @@ public:
         if (efficient) {
             dim = b.nx > max_ ? 0 : 1;
             c = (dim == 0 ? b.nx : b.ny) / 2;
-        } else if (!choose_cut(b, dim, c)) {
+        } else if (!choose_cut(b, p0, p1, dim, c)) {
             out.push_back(b);
             return;
         }
-        Box lo = b, hi = b;
-        if (dim == 0) {
-            lo.nx = c;
-            hi.i = b.i + c;
-            hi.nx = b.nx - c;
-        } else {
-            lo.ny = c;
-            hi.j = b.j + c;
-            hi.ny = b.ny - c;
+        const int edge = (dim == 0 ? b.i : b.j) + c;
+        const auto mid = std::stable_partition(pts_.begin() + p0, pts_.begin() + p1, [&](const Pt &p) {
+            return (dim == 0 ? p.i : p.j) < edge;
+        });
+        const size_t pm = (size_t)(mid - pts_.begin());
+        run(p0, pm, out);
+        run(pm, p1, out);
+    }
+
+    Box bounding_box(size_t p0, size_t p1) const
+    {
+        int i0 = pts_[p0].i, i1 = i0, j0 = pts_[p0].j, j1 = j0;
+        for (size_t k = p0 + 1; k < p1; ++k) {
+            const Pt &p = pts_[k];
+            i0 = std::min(i0, p.i); i1 = std::max(i1, p.i);
+            j0 = std::min(j0, p.j); j1 = std::max(j1, p.j);
         }
-        run(lo, out);
-        run(hi, out);
+        return Box{i0, j0, i1 - i0 + 1, j1 - j0 + 1};
     }
 
-private:
-    bool flag(int i, int j) const { return f_[(size_t)j * pitch_ + i] != 0; }
-
-    bool shrink(Box &b) const
-    {
-        int i0 = b.i + b.nx, i1 = b.i - 1, j0 = b.j + b.ny, j1 = b.j - 1;
-        for (int j = b.j; j < b.j + b.ny; ++j)
-            for (int i = b.i; i < b.i + b.nx; ++i)
-                if (flag(i, j)) {
-                    if (i < i0) i0 = i;
-                    if (i > i1) i1 = i;
-                    if (j < j0) j0 = j;
-                    if (j > j1) j1 = j;
-                }
-        if (i1 < i0) return false;
-        b = Box{i0, j0, i1 - i0 + 1, j1 - j0 + 1};
-        return true;
-    }
-
-    long long count(const Box &b) const
-    {
-        long long n = 0;
-        for (int j = b.j; j < b.j + b.ny; ++j)
-            for (int i = b.i; i < b.i + b.nx; ++i) n += flag(i, j);
-        return n;
-    }
-
-    void signatures(const Box &b, std::vector<long long> &sx, std::vector<long long> &sy) const
+    void signatures(const Box &b, size_t p0, size_t p1, std::vector<long long> &sx, std::vector<long long> &sy) const
     {
         sx.assign(b.nx, 0);
         sy.assign(b.ny, 0);
-        for (int j = 0; j < b.ny; ++j)
-            for (int i = 0; i < b.nx; ++i)
-                if (flag(b.i + i, b.j + j)) {
-                    ++sx[i];
-                    ++sy[j];
-                }
+        for (size_t k = p0; k < p1; ++k) {
+            ++sx[pts_[k].i - b.i];
+            ++sy[pts_[k].j - b.j];
+        }
     }
 
-    bool choose_cut(const Box &b, int &dim, int &cut) const
+    bool choose_cut(const Box &b, size_t p0, size_t p1, int &dim, int &cut) const
     {
         std::vector<long long> s[2];
-        signatures(b, s[0], s[1]);
+        signatures(b, p0, p1, s[0], s[1]);
         const int len[2] = {b.nx, b.ny};
         // holes
         int best_d = -1, best_c = -1;
@@ -146,8 +154,7 @@ private:
         return false;
     }
 
-    const int8_t *f_;
-    int pitch_;
+    std::vector<Pt> pts_;
     double eff_;
     int min_, max_;
 };
@@ -188,7 +195,7 @@ int32_t swe_cluster(const int8_t *flags, int32_t nx, int32_t ny, int32_t pitch, 
     if (!(efficiency > 0.0 && efficiency <= 1.0)) return fail(SWE_E_INVAL, "efficiency must be in (0, 1]");
     if (min_side < 1 || max_side < 2 * min_side) return fail(SWE_E_INVAL, "need min_side >= 1, max_side >= 2 min_side");
     std::vector<Box> out;
-    Clusterer(flags, pitch, efficiency, min_side, max_side).run(Box{0, 0, nx, ny}, out);
+    Clusterer(flags, nx, ny, pitch, efficiency, min_side, max_side).run(out);
     for (size_t k = 0; k < out.size() && (int32_t)k < max_boxes; ++k)
         boxes[k] = swe_box{out[k].i, out[k].j, out[k].nx, out[k].ny};
     return (int32_t)out.size();

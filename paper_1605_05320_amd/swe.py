@@ -514,13 +514,16 @@ def cluster(flags, efficiency=0.7, min_side=4, max_side=32):
     ny, nx = f.shape
     args = (f.ctypes.data_as(C.c_void_p), C.c_int32(nx), C.c_int32(ny), C.c_int32(nx), C.c_double(efficiency),
             C.c_int32(min_side), C.c_int32(max_side))
-    n = lib().swe_cluster(*args, None, C.c_int32(0))
+    cap = 1024
+    out = (swe_box * cap)()
+    n = lib().swe_cluster(*args, out, C.c_int32(cap))
     if n < 0:
         _check(n)
-    out = (swe_box * max(n, 1))()
-    n2 = lib().swe_cluster(*args, out, C.c_int32(n))
-    if n2 < 0:
-        _check(n2)
+    if n > cap:                      # more boxes than the first buffer holds
+        out = (swe_box * n)()
+        n2 = lib().swe_cluster(*args, out, C.c_int32(n))
+        if n2 < 0:
+            _check(n2)
     return [(b.i_lo, b.j_lo, b.nx, b.ny) for b in out[:n]]
 
 
