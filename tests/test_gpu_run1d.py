@@ -67,6 +67,8 @@ def run(S, n, K, tf, tol, per_step, flag_every=1, order=2, bc_lo=0, land=0, adj_
 CASES = [
     # n, K, tf, tol, extra
     (2000, 60, 10800.0, 1e-3, {}),                       # the 3 h shelf with 60 snapshots
+    (8, 4, 1800.0, 1e-3, {}),                            # one strip, mostly halo lanes
+    (60, 6, 1800.0, 1e-3, {"flag_every": 2, "ts": 600.0}),   # exactly one full strip
     (61, 8, 1800.0, 1e-3, {}),
     (119, 8, 1800.0, 1e-3, {"bc_lo": 1}),
     (121, 8, 1800.0, 1e-3, {"order": 1}),
@@ -88,4 +90,5 @@ def test_one_workgroup_equals_launch_per_step(S, case):
         assert np.array_equal(x.view(np.int64), y.view(np.int64))
     for x, y in zip(i0, i1):
         assert np.array_equal(x, y)
-    assert i0[2].any()
+    if n >= 60:
+        assert i0[2].any()
