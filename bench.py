@@ -165,6 +165,10 @@ def main():
     ap.add_argument("--flag-only", type=int, default=0, metavar="K",
                     help="run the --flag-n flag pass (34-snapshot window) K times and exit (profiler runs)")
     ap.add_argument("--flag-n", type=int, default=512, help="grid side of the --flag-only pass")
+    ap.add_argument("--run1d-only", type=int, default=0, metavar="K",
+                    help="run the 1D shelf problem (2000 cells, 3 h, 60 snapshots) K times and exit")
+    ap.add_argument("--run1d-per-step", type=int, default=0, choices=(0, 1),
+                    help="with --run1d-only: 1 launches every step (launch_per_step)")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
                     help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -217,6 +221,11 @@ def main():
             torch.empty_like(src).copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"flag_launches": args.flag_only}), flush=True)
+        return
+    if args.run1d_only > 0:
+        times = [round(run1d_shelf(S, torch, I, np, f64, launch_per_step=args.run1d_per_step), 4)
+                 for _ in range(args.run1d_only)]
+        print(json.dumps({"run1d_s": times, "launch_per_step": args.run1d_per_step}), flush=True)
         return
     if args.busy_only > 0:
         g, p, B, qa, qb, dt = busy_state(S, torch, I, np, f64, args.n)
@@ -483,6 +492,28 @@ def _box_fraction(bnd, K, nx, ny):
     b = bnd.view(K + 1, 4).cpu().tolist()
     a = [(r[1] - r[0] + 1) * (r[3] - r[2] + 1) if r[1] >= r[0] else 0 for r in b]
     return round(sum(a) / (len(a) * nx * ny), 4)
+
+
+def run1d_shelf(S, torch, I, np, f64, launch_per_step=0):
+    """One swe_run of the 1D shelf (2000 cells on [-400 km, 0], 3 h, 60
+    snapshots, tol 1e-3, flags every step); returns its wall time in s."""
+    n, K, tf, tol = 2000, 60, 10800.0, 1e-3
+    s1 = I.shelf1d(n, seed=0)
+    g = S.Grid(n, 1, s1.dx, 1.0, s1.x_lo)
+    B = torch.tensor(s1.B.reshape(1, n), **f64)
+    E = torch.tensor(s1.eta0.reshape(1, n), **f64)
+    frames = torch.zeros(K + 1, 2, 1, n, **f64)
+    q = [torch.zeros(1, n, **f64) for _ in range(2)]
+    acc = torch.zeros(1, n, dtype=torch.int8, device=B.device)
+    macc = torch.zeros(1, n, **f64)
+    pb = S.make_problem(g, S.Params(model=S.LINEAR), B, E, s1.target, 0.0, 0.0, tf, K, tol, frames, q, None, acc,
+                        macc, launch_per_step=launch_per_step)
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S.swe_run(pb, ws)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
 
 
 def run_bench(S, torch, I, np, f64):
