@@ -150,7 +150,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--graph", type=int, default=100,
                     help="attempts per captured HIP graph (0: plain stream launches)")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests in the serving trace (grids --serve-nmin..--serve-nmax a side)")
     ap.add_argument("--serve-nmin", type=int, default=256)
     ap.add_argument("--serve-nmax", type=int, default=1024)
