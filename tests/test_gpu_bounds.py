@@ -167,3 +167,52 @@ def test_run_with_and_without_skipping_bit_identical(S, shape):
     for x, y in zip(res[0][1], res[1][1]):
         assert np.array_equal(x, y)
     assert res[0][1][1].any()
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("interp", [False, True])
+def test_random_boxes_bit_identical(S, seed, interp):
+    """Snapshots that are non-zero only in random rectangles (single cells,
+    whole rows, the grid's corners and edges, empty snapshots), on a ragged
+    grid: flags and m with the boxes equal those without, for random windows."""
+    rng = np.random.default_rng(100 + seed)
+    nx, ny, K = int(rng.integers(70, 200)), int(rng.integers(40, 130)), 9
+    ax, ay = (nx // 2 + 3, ny // 2 + 2) if interp else (nx, ny)
+    frames = np.zeros((K + 1, 3, ay, ax))
+    for k in range(K + 1):
+        kind = rng.integers(0, 5)
+        if kind == 0:
+            continue                                            # zero everywhere
+        if kind == 1:
+            i, j = int(rng.integers(0, ax)), int(rng.integers(0, ay))
+            frames[k, int(rng.integers(0, 3)), j, i] = rng.normal()    # one cell, one plane
+            continue
+        i0, j0 = int(rng.integers(0, ax)), int(rng.integers(0, ay))
+        i1, j1 = int(rng.integers(i0, ax)) + 1, int(rng.integers(j0, ay)) + 1
+        if kind == 3:
+            i0, i1 = 0, ax                                       # whole rows
+        frames[k, :, j0:j1, i0:i1] = rng.normal(size=(3, j1 - j0, i1 - i0))
+    b = I.basin(max(nx, ny), seed)
+    B = b.B[:ny, :nx]
+    h = np.maximum(0.0, b.eta0[:ny, :nx] + rng.uniform(-0.05, 0.05, (ny, nx)) - B)
+    q = [dev(h), dev(0.3 * h), dev(-0.2 * h)]
+    g = S.Grid(nx, ny, 1000.0, 1000.0)
+    fr = dev(frames)
+    bd = torch.empty(4 * (K + 1), dtype=torch.int32, device=DEV)
+    ga = S.Grid(ax, ay, 2000.0, 2000.0)
+    S.adj_frame_bounds(ga if interp else g, fr, K, bd)
+    Bd = dev(B)
+    Ba = dev(np.full((ay, ax), -1000.0))
+    for lo, hi in [(0, K), (int(rng.integers(0, K)), K), (3, 3), (K, K - 1)]:
+        res = []
+        for use in (None, bd):
+            fl = torch.empty(ny, nx, dtype=torch.int8, device=DEV)
+            m = torch.empty(ny, nx, dtype=torch.float64, device=DEV)
+            if interp:
+                S.adj_flag_interp(g, S.Params(), Bd, q, ga, Ba, fr, K, lo, hi, 1e-3, fl, m, bounds=use)
+            else:
+                S.adj_flag(g, S.Params(), Bd, q, fr, K, lo, hi, 1e-3, fl, m, bounds=use)
+            torch.cuda.synchronize()
+            res.append((host(fl), host(m)))
+        assert np.array_equal(res[0][0], res[1][0]), (lo, hi)
+        assert np.array_equal(res[0][1].view(np.int64), res[1][1].view(np.int64)), (lo, hi)

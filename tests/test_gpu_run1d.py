@@ -92,3 +92,23 @@ def test_one_workgroup_equals_launch_per_step(S, case):
         assert np.array_equal(x, y)
     if n >= 60:
         assert i0[2].any()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_problems_one_workgroup_equals_launch_per_step(S, seed):
+    """Random sizes (including the largest grid of one workgroup), boundaries,
+    orders, land, cadences, windows and adjoint grids."""
+    rng = np.random.default_rng(500 + seed)
+    n = int(rng.choice([int(rng.integers(2, 130)), int(rng.integers(130, 3841)), 3840]))
+    kw = dict(flag_every=int(rng.integers(1, 4)), order=int(rng.integers(1, 3)), bc_lo=int(rng.integers(0, 2)),
+              land=int(rng.integers(0, n // 4 + 1)), ts=float(rng.choice([0.0, 600.0])), seed=int(rng.integers(0, 8)))
+    if n >= 16 and rng.random() < 0.4:
+        kw["adj_n"] = int(rng.integers(8, n // 2 + 2))
+    K, tf = int(rng.integers(1, 13)), float(rng.choice([900.0, 1800.0]))
+    r0, f0, i0 = run(S, n, K, tf, 1e-3, 0, **kw)
+    r1, f1, i1 = run(S, n, K, tf, 1e-3, 1, **kw)
+    assert r0 == r1, (n, K, kw, r0, r1)
+    for x, y in zip(f0, f1):
+        assert np.array_equal(x.view(np.int64), y.view(np.int64)), (n, K, kw)
+    for x, y in zip(i0, i1):
+        assert np.array_equal(x, y), (n, K, kw)
