@@ -744,11 +744,16 @@ swe_status swe_run(const swe_problem *pb, void *workspace, size_t workspace_byte
         double tout = (j == K) ? pb->tf : pb->t0 + j * ds;
         if (j == 1) {
             if ((st = swe_ctl_set(w.ctl, pb->t0, dt0, tout, 0, stream)) != SWE_OK) return st;
+            HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
         } else {
+            // the host's copy of the control block is the state at the last
+            // output time, which the retarget leaves as it is but for the new
+            // output time (and dt clamped to it): the attempt count below
+            // comes out the same from either dt, so no read is needed
             if ((st = swe_ctl_retarget(w.ctl, tout, stream)) != SWE_OK) return st;
+            hc.s.done = 0;
         }
-        HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
         fl.flags_final = pb->flags_at ? pb->flags_at + (size_t)j * plane : w.flags;
         int rounds = 0, stalled = 0;
         while (!hc.s.done) {
