@@ -63,8 +63,11 @@ int wave_slots()
 // and finish early while the pairs on the others set the launch's time
 // (measured on 1024^2 with 103 marches of 10 rows per strip: a wavefront
 // alone on its SIMD took 30 us, a pair 30 and 47 us).  Heights differ by at
-// most one row.  24 rows when the grid is too large for one wave of
-// wavefronts (measured best of 16 to 64 rows on a 4096^2 grid).
+// most one row.  While one wave of wavefronts needs marches of at most 56
+// rows it is still the faster choice (2048^2 with waves on every edge: 36
+// rows in one wave 135 us, 24 rows in one and a half waves 151 us; 2560^2:
+// 54-55 rows 205 us, 24 rows 230 us); beyond, marches of 24 rows (measured best
+// of 16 to 138 rows on a 4096^2 grid, and even with 78 rows on 3072^2).
 // SWE_MARCH_ROWS forces ly rows for every chunk (tuning sweeps).
 void march_rows(int nx, int ny, int &ly, int &lyr)
 {
@@ -77,7 +80,7 @@ void march_rows(int nx, int ny, int &ly, int &lyr)
     if (forced > 0) { ly = forced; return; }
     const long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
     long long c = std::min<long long>(wave_slots() / strips, ny / 2);
-    if (c < 1 || (ny + c - 1) / c > 24) c = (ny + 23) / 24;
+    if (c < 1 || (ny + c - 1) / c > 56) c = (ny + 23) / 24;
     ly = (int)(ny / c);
     lyr = (int)(ny % c);
 }
