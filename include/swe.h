@@ -298,11 +298,12 @@ typedef enum {
  * A pass is one wavefront's work: up to 64 lanes, each lane a column of one
  * patch strip (the strip's columns plus 2 ghost columns each side); all its
  * patches are marched over rows pass_row0 .. pass_row0 + pass_rows - 1.  A job
- * is a run of passes done by one wavefront.  With chunk_rows > 0 every pass
- * taller than chunk_rows is cut into passes of at most chunk_rows rows (each
- * its own job: more wavefronts for small levels, at the cost of the chunks'
- * halo rows); with chunk_rows = 0 a pass covers its patches' full height and
- * every patch lies within one job.
+ * is a run of passes (the strips of one patch), and jobs come longest first;
+ * both launch modes take the passes in this order, each pass on its own.
+ * With chunk_rows > 0 every pass taller than chunk_rows is cut into passes of
+ * at most chunk_rows rows (each its own job: more wavefronts for small
+ * levels, at the cost of the chunks' halo rows); with chunk_rows = 0 a pass
+ * covers its patches' full height and every patch lies within one job.
  *   lanes:     n_passes*64 int64, lane = (patch << 32) | (role << 16) | (col + 32768),
  *              role bit 0: output column, bit 1: its west edge counts for the
  *              Courant number; -1 for an idle lane
@@ -317,6 +318,9 @@ SWE_API int32_t swe_level_schedule(const swe_patch *patches, int32_t n_patches, 
                                    int64_t *lanes, int32_t *pass_rows, int32_t *pass_row0, int32_t *job_pass,
                                    int32_t *n_jobs);
 
+/* 32-bit words of a level's barrier (swe_level.sync). */
+#define SWE_LEVEL_SYNC_WORDS 4096
+
 /* A level on the device. */
 typedef struct {
     int32_t n_patches, n_passes, n_jobs;
@@ -325,7 +329,8 @@ typedef struct {
     const int64_t *lanes;       /* device, from swe_level_schedule */
     const int32_t *pass_rows;   /* device */
     const int32_t *job_pass;    /* device */
-    uint32_t *sync;             /* device, 4 words zeroed once by the caller (persistent mode) */
+    uint32_t *sync;             /* device, SWE_LEVEL_SYNC_WORDS words zeroed once by the caller
+                                   (persistent mode); word 2 is the barrier's error word */
     const int32_t *pass_row0;   /* device, first row of each pass (NULL: all 0) */
 } swe_level;
 
@@ -334,15 +339,16 @@ typedef struct {
  * model) under device-side control `ctl` (the rule of swe_advance, with the
  * Courant number the max over all patches).  persistent = 0: one launch per
  * attempt, one wavefront per pass (graph-capturable).  persistent = 1: a
- * single cooperative launch of at most one wavefront per resident slot runs
- * all attempts, the wavefronts meeting at a grid barrier after each attempt;
+ * single cooperative launch of at most one wavefront per resident slot, in
+ * workgroups of 8, runs all attempts, the workgroups meeting at a grid
+ * barrier after each attempt;
  * a barrier that does not open within a bounded spin sets sync[2] to nonzero
  * and the launch ends early (the caller checks sync[2]; the state is then
- * not a valid result).  Each patch is owned by one wavefront, so patches never
- * exchange data within a launch; a level cut into row chunks (chunk_rows > 0)
- * is therefore refused in persistent mode (SWE_E_INVAL): its chunks read
- * halo rows that other wavefronts wrote in the previous attempt.  State in
- * a (cur = 0) / b (cur = 1); B: bottom planes of the level.  Enqueue only.
+ * not a valid result).  The barrier orders each attempt's stores before the
+ * next attempt's loads on every wavefront, so a level cut into row chunks
+ * (chunk_rows > 0), whose chunks read halo rows that other wavefronts stored
+ * in the previous attempt, runs in either mode.  State in a (cur = 0) /
+ * b (cur = 1); B: bottom planes of the level.  Enqueue only.
  */
 SWE_API swe_status swe_level_advance(const swe_level *level, const swe_params *prm, const double *B,
                                      swe_fields a, swe_fields b, swe_ctl *ctl, int32_t n_steps,
@@ -362,8 +368,7 @@ typedef struct {
  * n_trial attempts from dt with the control rule, time them with HIP events,
  * and compare the resulting state bit for bit with the first candidate's (kept
  * in `ref`).  Writes 2*n_levels entries to `out` (host) and the index of the
- * fastest into *best; the persistent mode of a level cut into row chunks is
- * not run (its entry has us_per_attempt = -1).  Returns SWE_E_HIP if two candidates disagree in any
+ * fastest into *best.  Returns SWE_E_HIP if two candidates disagree in any
  * bit (*mismatch, device int32, receives the count).  Synchronises `stream`.
  */
 SWE_API swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, const swe_params *prm,

@@ -482,7 +482,7 @@ template <class M>
 __device__ __forceinline__ void level_pass(const KParams &P, const LevelArgs &L, int pass, double &cfl,
                                            int &nclamp, int &nbad)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
     const long long v = L.lanes[(size_t)pass * WAVE + lane];
     const bool idle = v < 0;
     const int patch = idle ? 0 : (int)(v >> 32);
@@ -509,52 +509,116 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_step(KParams P, LevelArgs L)
     march_epilogue(P, threadIdx.x, cfl, nclamp, nbad);
 }
 
-// Grid barrier of the persistent level kernel (generation counter; the last
-// wavefront to arrive resets the count and opens the next generation).  Each
-// wavefront's Courant-number atomic is complete (s_waitcnt) before it
-// arrives.  A barrier that does not open within a bounded spin raises the
-// error word and lets the wavefront go on, so every wavefront always reaches
-// the end of the kernel.
-__device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nw)
+// Workgroup state of the persistent level kernel in LDS: the job counter,
+// the barrier's verdict, and each wavefront's Courant number (bit pattern)
+// and counts of the attempt.
+struct LvlShared {
+    int next_job;
+    int ok;
+    unsigned long long cfl_bits[LVL_WAVES];
+    int ncl[LVL_WAVES], nbad[LVL_WAVES];
+};
+
+// Grid barrier of the persistent level kernel, one arrival per workgroup.
+// Each wavefront leaves its Courant number and counts of the attempt in LDS
+// and has its stores complete (in its XCD's L2) before the workgroup meets at
+// s_barrier.  Thread 0 then adds the workgroup's Courant number and counts to
+// the attempt's ring line (one atomic each for the workgroup: the largest bit
+// pattern and the sums, the same words as one atomic per wavefront would
+// leave), releases everything to device scope (written back past the L2),
+// arrives, waits for the generation word to move on, and acquires (caches
+// invalidated), so rows that workgroups on other XCDs stored in this attempt
+// (the halo rows of a patch cut into row chunks) are read as stored.
+// Arrivals go up a two-level tree (LVL_GROUP workgroups per counter, then one
+// arrival per counter at the top); with the 256 workgroups of one wave of a
+// 256-CU part that is one counter and the top (measured: one counter for all
+// costs less than counters of 8 or 16 workgroups, whose last arrivals wait for
+// a second atomic).  A barrier that does not open within a bounded spin raises
+// the error word and lets the workgroup go on, so every wavefront always
+// reaches the end of the kernel.  Thread 0 also resets the workgroup's job
+// counter for the next attempt.  sync words: [1] generation, [2] error,
+// [3] top-level count; counter of group k at word LVL_SYNC_LINE * (k + 1)
+// (one 128-byte line each).
+__device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nb, unsigned long long *line,
+                                              LvlShared &sh)
 {
-    int ok = 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_s_waitcnt(0);
-        unsigned g = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned arrived = __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nw - 1) {
-            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sh.next_job = 0;
+        unsigned long long m = 0;
+        int sc = 0, sb = 0;
+#pragma unroll
+        for (int k = 0; k < LVL_WAVES; ++k) {
+            m = sh.cfl_bits[k] > m ? sh.cfl_bits[k] : m;
+            sc += sh.ncl[k];
+            sb += sh.nbad[k];
+        }
+        if (sc) atomicAdd(line + 1, (unsigned long long)sc);
+        if (sb) atomicAdd(line + 2, (unsigned long long)sb);
+        atomicMax(line, m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int ok = 1;
+        const unsigned g = __hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned grp = blockIdx.x / LVL_GROUP, ngrp = (nb + LVL_GROUP - 1) / LVL_GROUP;
+        const unsigned in_grp = min(nb - grp * LVL_GROUP, (unsigned)LVL_GROUP);
+        uint32_t *cnt = &sync[LVL_SYNC_LINE * (grp + 1)];
+        bool last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1;
+        if (last) {
+            // the group's releases precede its arrivals: pass them on
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = __hip_atomic_fetch_add(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1;
+        }
+        if (last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(&sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
             __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             long long spins = 0;
             while (__hip_atomic_load(&sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > (1ll << 22)) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1ll << 23)) {
                     __hip_atomic_fetch_or(&sync[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        sh.ok = ok;
     }
-    return __shfl(ok, 0, WAVE) != 0;
+    __syncthreads();
+    return sh.ok != 0;
 }
 
-// All attempts of a level in one launch: wavefront w does jobs w, w + nw, ...
-// of every attempt; after each attempt the wavefronts meet at the barrier and
-// each applies the control rule to the level's Courant number itself.
-__global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelArgs L, int n_steps)
+// All attempts of a level in one launch of workgroups of LVL_WAVES
+// wavefronts.  The unit of work is the pass, as in the launch per attempt: a
+// pass reads only the previous attempt's state (the planes alternate), so the
+// passes of one attempt never depend on each other, and the strips and row
+// chunks of one patch may run on different wavefronts.  Workgroup b owns
+// passes k nb + b for even k and k nb + nb-1-b for odd k (nb workgroups; the
+// passes come in the schedule's job order, longest first, so the snake order
+// gives every workgroup a like share), and its wavefronts take them in that
+// order from a counter in LDS as they become free.  After each attempt the
+// workgroups meet at the barrier and every wavefront applies the control rule
+// to the level's Courant number itself.
+__global__ void __launch_bounds__(WAVE * LVL_WAVES, 1) k_level_persistent(KParams P, LevelArgs L, int n_steps)
 {
+    __shared__ LvlShared sh;
     swe_ctl *c = P.ctl;
-    const unsigned nw = gridDim.x;
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int nb = gridDim.x, b = blockIdx.x;
+    if (threadIdx.x == 0) sh.next_job = 0;
+    __syncthreads();
     swe_ctl_state S = c->s;
     unsigned long long last_bits = 0;
     bool ran = false;
     for (int a = 0; a < n_steps && !S.done; ++a) {
         if (blockIdx.x == 0 && threadIdx.x < SWE_CTL_SPREAD)
-            for (int w = 0; w < 3; ++w)
-                __hip_atomic_store(&c->ring[(a + 1) % 3][threadIdx.x][w], 0ull, __ATOMIC_RELAXED,
+            for (int k = 0; k < 3; ++k)
+                __hip_atomic_store(&c->ring[(a + 1) % 3][threadIdx.x][k], 0ull, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         KParams Q = P;
         Q.dt = S.dt;
@@ -566,10 +630,27 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_persistent(KParams P, LevelAr
         aim_ring(Q, c, a % 3);
         double cfl = 0.0;
         int nclamp = 0, nbad = 0;
-        for (int j = blockIdx.x; j < L.n_jobs; j += nw)
-            for (int ps = L.job_pass[j]; ps < L.job_pass[j + 1]; ++ps) level_pass<NL>(Q, L, ps, cfl, nclamp, nbad);
-        march_epilogue(Q, threadIdx.x, cfl, nclamp, nbad);
-        if (!level_barrier(L.sync, nw)) break;
+        for (;;) {
+            int k = 0;
+            if (lane == 0) k = atomicAdd(&sh.next_job, 1);
+            k = __shfl(k, 0, WAVE);
+            const long long ps = (long long)k * nb + ((k & 1) ? nb - 1 - b : b);
+            if (ps >= L.n_passes) break;
+            level_pass<NL>(Q, L, (int)ps, cfl, nclamp, nbad);
+        }
+        cfl = wave_max(cfl);
+        int sc = 0, sb = 0;
+        if (__any(nclamp > 0 || nbad > 0)) {
+            sc = wave_sum(nclamp);
+            sb = wave_sum(nbad);
+        }
+        if (lane == 0) {
+            sh.cfl_bits[wave] = (unsigned long long)__double_as_longlong(cfl);
+            sh.ncl[wave] = sc;
+            sh.nbad[wave] = sb;
+        }
+        // the job counter is read again only after the barrier's closing s_barrier
+        if (!level_barrier(L.sync, nb, Q.cfl_bits + (size_t)(b % Q.cfl_spread) * Q.cfl_stride, sh)) break;
         last_bits = 0;
         for (int j = 0; j < SWE_CTL_SPREAD; ++j) {
             const unsigned long long v =
@@ -1445,8 +1526,9 @@ int level_persistent_capacity()
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_level_persistent, WAVE, 0) != hipSuccess) return 0;
-    return cus * per;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_level_persistent, WAVE * LVL_WAVES, 0) != hipSuccess)
+        return 0;
+    return std::min(cus * per, LVL_MAX_BLOCKS);
 }
 
 hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_steps, int nw, hipStream_t s)
@@ -1455,7 +1537,7 @@ hipError_t launch_level_persistent(const KParams &P, const LevelArgs &L, int n_s
     LevelArgs l = L;
     int n = n_steps;
     void *args[] = {&p, &l, &n};
-    return hipLaunchCooperativeKernel((const void *)k_level_persistent, dim3(nw), dim3(WAVE), args, 0, s);
+    return hipLaunchCooperativeKernel((const void *)k_level_persistent, dim3(nw), dim3(WAVE * LVL_WAVES), args, 0, s);
 }
 
 // Count elements whose bit patterns differ (schedule-invariance checks).

@@ -187,8 +187,6 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
     if (!swe::params_in_range(prm))
         return fail(SWE_E_INVAL, "g = %g and dry_tol = %g must lie in [1e-100, 1e100]", prm->g, prm->dry_tol);
     if (persistent && !L->sync) return fail(SWE_E_INVAL, "persistent mode needs the sync words");
-    if (persistent && L->chunk_rows > 0)
-        return fail(SWE_E_INVAL, "persistent mode needs whole-patch jobs (chunk_rows = 0)");
     if (n_steps == 0) return SWE_OK;
 
     swe::KParams k;
@@ -228,7 +226,7 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
     }
     int cap = swe::level_persistent_capacity();
     if (cap < 1) return fail(SWE_E_HIP, "cannot size the persistent launch");
-    int nw = std::min(cap, L->n_jobs);
+    int nw = std::min(cap, (L->n_passes + swe::LVL_WAVES - 1) / swe::LVL_WAVES);
     hipError_t e = swe::launch_level_persistent(k, la, n_steps, nw, s);
     if (e != hipSuccess) return fail(SWE_E_HIP, "persistent level launch: %s", hipGetErrorString(e));
     return SWE_OK;
@@ -260,14 +258,6 @@ swe_status swe_level_tune(const swe_level *const *levels, int32_t n_levels, cons
     int nout = 0;
     bool have_ref = false;
     auto run_candidate = [&](int k, int pers) -> swe_status {
-        if (pers && levels[k]->chunk_rows > 0) {
-            // chunked levels only run one launch per attempt
-            out[nout].level = k;
-            out[nout].persistent = pers;
-            out[nout].us_per_attempt = -1.0;
-            ++nout;
-            return SWE_OK;
-        }
         swe_status st;
         const double *src[3] = {init.f0, init.f1, init.f2};
         double *dst[3] = {work_a.f0, work_a.f1, work_a.f2};

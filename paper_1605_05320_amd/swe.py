@@ -63,6 +63,7 @@ class swe_result(C.Structure):
 
 
 CTL_SPREAD = 8      # SWE_CTL_SPREAD
+LEVEL_SYNC_WORDS = 4096   # SWE_LEVEL_SYNC_WORDS
 
 
 class swe_ctl_state(C.Structure):
@@ -488,7 +489,7 @@ class Level:
         self.rows_t = torch.tensor(rows, device=device)
         self.row0_t = torch.tensor(row0, device=device)
         self.jp_t = torch.tensor(jp, device=device)
-        self.sync_t = torch.zeros(4, dtype=torch.int32, device=device)
+        self.sync_t = torch.zeros(LEVEL_SYNC_WORDS, dtype=torch.int32, device=device)
         self.c = swe_level(len(tab), len(rows), len(jp) - 1, chunk_rows, self.patches_t.data_ptr(),
                            self.lanes_t.data_ptr(), self.rows_t.data_ptr(), self.jp_t.data_ptr(),
                            self.sync_t.data_ptr(), self.row0_t.data_ptr())

@@ -76,6 +76,23 @@ def test_ctypes_mirrors_match_the_header(S, tmp_path):
             assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, f"{name}.{f[0]}"
 
 
+def test_binding_constants_match_the_header(S, tmp_path):
+    consts = {"SWE_CTL_SPREAD": S.CTL_SPREAD, "SWE_LEVEL_SYNC_WORDS": S.LEVEL_SYNC_WORDS,
+              "SWE_STATIC_WORKSPACE_BYTES": S.STATIC_WORKSPACE_BYTES}
+    lines = ["#include <stdio.h>", '#include "swe.h"', "int main(void) {"]
+    lines += [f'printf("{k} %llu\\n", (unsigned long long)({k}));' for k in consts]
+    lines += ["return 0;", "}"]
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for k, v in consts.items():
+        assert int(got[k]) == v, k
+
+
 def test_window_matches_oracle(S, oracle):
     rng = np.random.default_rng(11)
     for K in (1, 3, 8, 32):

@@ -222,11 +222,12 @@ def _oracle_level(O, ps, q, dt, n_steps, cfl_d=0.9, cfl_max=1.0):
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("kind,chunk,persistent", [(1, 16, 0), (1, 0, 1)])
+@pytest.mark.parametrize("kind,chunk,persistent", [(1, 16, 0), (1, 0, 1), (1, 16, 1)])
 def test_full_level_3000_patches(oracle, S, kind, chunk, persistent):
     """The benchmark's level (3000 patches of 8..64 cells a side, seed 4): the
-    tuned schedule (packed, 16-row chunks, one launch per attempt) and the
-    persistent launch of whole packed patches, 10 attempts, every patch."""
+    packed schedule in 16-row chunks with one launch per attempt and with one
+    persistent launch (more jobs than resident wavefronts), and the persistent
+    launch of whole packed patches, 10 attempts, every patch."""
     O = oracle
     ps = I.patches(3000, seed=4)
     print(f"3000-patch level: kind={kind} chunk={chunk} persistent={persistent}", flush=True)

@@ -79,7 +79,8 @@ def to_arena(arrs):
 
 
 @pytest.mark.parametrize("kind,persistent,chunk", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (1, 0, 16),
-                                                    (1, 0, 12), (0, 0, 9), (1, 0, 1)])
+                                                    (1, 0, 12), (0, 0, 9), (1, 0, 1), (1, 1, 16), (0, 1, 9),
+                                                    (1, 1, 1)])
 def test_level_parity(oracle, S, setup, kind, persistent, chunk):
     ps, B, q, dt0 = setup
     n_steps = 7
@@ -116,12 +117,29 @@ def test_level_parity(oracle, S, setup, kind, persistent, chunk):
     print(f"level kind={kind} persistent={persistent} chunk={chunk}: bit-exact={exact}")
 
 
-def test_persistent_refuses_row_chunks(S, setup):
+@pytest.mark.parametrize("chunk", [2, 5])
+def test_persistent_row_chunks_match_per_step(S, setup, chunk):
+    """Row chunks of one patch on different wavefronts of the persistent
+    launch: the halo rows each chunk reads were stored by other wavefronts in
+    the previous attempt.  The result equals the launch-per-step run of the
+    same schedule bit for bit, with the same accepted and rejected attempts."""
     ps, B, q, dt0 = setup
     tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
-    lvl = S.Level(tab, 1, chunk_rows=16)
-    z = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
-    w = [torch.zeros(ncell, dtype=torch.float64, device="cuda") for _ in range(3)]
-    ctl = S.new_ctl()
-    with pytest.raises(S.SweError):
-        S.level_advance(lvl, S.Params(), z[0], z, w, ctl, 3, 1)
+    lvl = S.Level(tab, 1, chunk_rows=chunk)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    Bd = dev(to_arena(B))
+    res = []
+    for persistent in (0, 1):
+        a = [dev(to_arena([qq[c] for qq in q])) for c in range(3)]
+        b = [torch.full_like(x, float("nan")) for x in a]
+        ctl = S.new_ctl()
+        S.swe_ctl_set(ctl, 0.0, 1.6 * dt0, 1e30, 0)
+        S.level_advance(lvl, S.Params(), Bd, a, b, ctl, 9, persistent)
+        torch.cuda.synchronize()
+        assert int(lvl.sync_t[2].item()) == 0
+        c = S.read_ctl(ctl)
+        res.append(((c.n_accepted, c.n_rejected, c.t, c.dt), [x.cpu().numpy() for x in (a if c.cur == 0 else b)]))
+    assert res[0][0] == res[1][0] and res[0][0][1] >= 1
+    for x, y in zip(res[0][1], res[1][1]):
+        assert np.array_equal(x.view(np.int64), y.view(np.int64))
+    print(f"chunk={chunk}: {lvl.c.n_jobs} jobs, persistent equals per-step")
