@@ -604,7 +604,7 @@ __device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nb, unsig
 // order from a counter in LDS as they become free.  After each attempt the
 // workgroups meet at the barrier and every wavefront applies the control rule
 // to the level's Courant number itself.
-__global__ void __launch_bounds__(WAVE * LVL_WAVES, 1) k_level_persistent(KParams P, LevelArgs L, int n_steps)
+__global__ void __launch_bounds__(WAVE * LVL_WAVES, 2) k_level_persistent(KParams P, LevelArgs L, int n_steps)
 {
     __shared__ LvlShared sh;
     swe_ctl *c = P.ctl;

@@ -542,13 +542,13 @@ def test_full_size_1024_sampled_steps(oracle, S):
     assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
 
 
-@pytest.mark.parametrize("nx,ny", [(1024, 1024), (4096, 720)])
+@pytest.mark.parametrize("nx,ny", [(1024, 1024), (2048, 2048), (2560, 2560), (4096, 720)])
 def test_large_grids_waves_on_every_edge(oracle, S, nx, ny):
     """Surface noise on every wet cell, so that no row is at rest and the
     step runs its subcritical all-wet forms on most wavefronts: the 1024^2
-    benchmark grid (10-row marches, all resident) and a 4096-wide grid whose
-    launch exceeds the resident slots (24-row marches).  Two steps, every
-    element compared."""
+    benchmark grid (9-10-row marches), 2048^2 and 2560^2 (one wave of 35-36-
+    and 54-55-row marches), and a 4096-wide grid whose launch exceeds the
+    resident slots (23-24-row marches).  Two steps, every element compared."""
     O = oracle
     b = I.basin(nx, 2, ny=ny)
     go, gs = pair_grids(O, S, nx, ny, b.grid.dx, b.grid.dy)
