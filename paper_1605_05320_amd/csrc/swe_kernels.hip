@@ -669,6 +669,11 @@ __global__ void __launch_bounds__(WAVE * LVL_WAVES, 2) k_level_persistent(KParam
         }
         ran = true;
     }
+    // Workgroup 0 leaves the loop after the last attempt or after an accepted
+    // final step.  Another workgroup may read the last attempt's ring words
+    // only after the clear below; it then takes a Courant number of 0, which
+    // gives the same decision (accepted) in the second case and no decision
+    // that matters in the first, and only workgroup 0's state is stored.
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         c->s = S;
         if (ran) c->cfl_bits = last_bits;
