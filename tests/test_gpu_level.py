@@ -143,3 +143,44 @@ def test_persistent_row_chunks_match_per_step(S, setup, chunk):
     for x, y in zip(res[0][1], res[1][1]):
         assert np.array_equal(x.view(np.int64), y.view(np.int64))
     print(f"chunk={chunk}: {lvl.c.n_jobs} jobs, persistent equals per-step")
+
+@pytest.mark.parametrize("seed,n,kind,chunk", [(11, 3, 1, 0), (12, 5, 0, 4), (13, 120, 1, 7), (14, 400, 0, 16),
+                                               (15, 400, 1, 3)])
+def test_persistent_random_levels_match_per_step(oracle, S, seed, n, kind, chunk):
+    """Random patch sets (from a single workgroup with idle wavefronts to
+    more passes than resident wavefronts), both schedules, whole patches and
+    row chunks, waves on every wet cell and a first dt that gets rejected:
+    the persistent launch equals the launch per attempt bit for bit."""
+    O = oracle
+    ps = I.patches(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    q, dts = [], []
+    for k in range(n):
+        g = O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k])
+        e = 20.0 * ps.eta0[k] + rng.uniform(-0.05, 0.05, ps.B[k].shape)
+        qk = O.init_state(g, O.Params(), O.NONLINEAR, ps.B[k], e)
+        q.append(qk)
+        d = O.dt0(g, O.Params(), O.NONLINEAR, ps.B[k], *qk)
+        if d > 0:
+            dts.append(d)
+    dt0 = 1.6 * min(dts)
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    lvl = S.Level(tab, kind, chunk_rows=chunk)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    Bd = dev(to_arena(ps.B))
+    res = []
+    for persistent in (0, 1):
+        a = [dev(to_arena([qq[c] for qq in q])) for c in range(3)]
+        b = [torch.full_like(x, float("nan")) for x in a]
+        ctl = S.new_ctl()
+        S.swe_ctl_set(ctl, 0.0, dt0, 1e30, 0)
+        S.level_advance(lvl, S.Params(), Bd, a, b, ctl, 8, persistent)
+        torch.cuda.synchronize()
+        assert int(lvl.sync_t[2].item()) == 0
+        c = S.read_ctl(ctl)
+        res.append(((c.n_accepted, c.n_rejected, c.t, c.dt, c.n_clamped, c.n_nonfinite),
+                    [x.cpu().numpy() for x in (a if c.cur == 0 else b)]))
+    assert res[0][0] == res[1][0] and res[0][0][1] >= 1 and res[0][0][0] >= 1
+    for x, y in zip(res[0][1], res[1][1]):
+        assert np.array_equal(x.view(np.int64), y.view(np.int64))
+    print(f"seed={seed}: {n} patches, {lvl.c.n_passes} passes, persistent equals per-step")
