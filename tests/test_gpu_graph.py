@@ -1,5 +1,6 @@
 """HIP-graph capture of the device-controlled stepping (the form the headline
-step is timed in) and of a batched level's launch-per-step advance: a graph of
+step is timed in) and of a batched level's advance (launch per attempt, and
+the one persistent launch): a graph of
 K attempts, captured once, is replayed several times with eager work and
 synchronisations in between, and the state and control block after every
 replay equal, bit for bit, those of the same attempts issued eagerly."""
@@ -85,7 +86,10 @@ def test_advance_graph_replays_match_eager(S, n, ny, K):
     assert S.read_ctl(ctl_g).s.n_rejected >= 1
 
 
-def test_level_graph_replays_match_eager(S):
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_level_graph_replays_match_eager(S, persistent):
+    """The level's advance of 5 attempts in 16-row chunks, one launch per
+    attempt or one persistent (cooperative) launch, captured once."""
     ps = I.patches(200, seed=4)
     tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
     B = torch.tensor(np.concatenate([x.ravel() for x in ps.B]), **F64)
@@ -109,6 +113,7 @@ def test_level_graph_replays_match_eager(S):
     S.swe_ctl_set(ctl_e, 0.0, dt0, 1.0e30, 0)
     S.swe_ctl_set(ctl_g, 0.0, dt0, 1.0e30, 0)
     torch.cuda.synchronize()
-    check_replays(S, lambda: S.level_advance(lv, p, B, ea, eb, ctl_e, 5),
-                  lambda st: S.level_advance(lv, p, B, ga, gb, ctl_g, 5, 0, stream=st),
+    check_replays(S, lambda: S.level_advance(lv, p, B, ea, eb, ctl_e, 5, persistent),
+                  lambda st: S.level_advance(lv, p, B, ga, gb, ctl_g, 5, persistent, stream=st),
                   ctl_e, ctl_g, ea, eb, ga, gb)
+    assert int(lv.sync_t[2].item()) == 0
