@@ -530,10 +530,10 @@ struct LvlShared {
 // invalidated), so rows that workgroups on other XCDs stored in this attempt
 // (the halo rows of a patch cut into row chunks) are read as stored.
 // Arrivals go up a two-level tree (LVL_GROUP workgroups per counter, then one
-// arrival per counter at the top); with the 256 workgroups of one wave of a
-// 256-CU part that is one counter and the top (measured: one counter for all
-// costs less than counters of 8 or 16 workgroups, whose last arrivals wait for
-// a second atomic).  A barrier that does not open within a bounded spin raises
+// arrival per counter at the top) when there is more than one counter; the
+// 256 workgroups of one wave of a 256-CU part arrive at a single counter
+// (measured: one counter for all costs less than counters of 8 or 16
+// workgroups, whose last arrivals wait for a second atomic).  A barrier that does not open within a bounded spin raises
 // the error word and lets the workgroup go on, so every wavefront always
 // reaches the end of the kernel.  Thread 0 also resets the workgroup's job
 // counter for the next attempt.  sync words: [1] generation, [2] error,
@@ -564,15 +564,17 @@ __device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nb, unsig
         const unsigned in_grp = min(nb - grp * LVL_GROUP, (unsigned)LVL_GROUP);
         uint32_t *cnt = &sync[LVL_SYNC_LINE * (grp + 1)];
         bool last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == in_grp - 1;
-        if (last) {
+        if (last && ngrp > 1) {
             // the group's releases precede its arrivals: pass them on
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = __hip_atomic_fetch_add(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1;
+            cnt = &sync[3];
+            last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngrp - 1;
         }
         if (last) {
+            // every release precedes its arrival: pass them on to the waiters
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(&sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
             __hip_atomic_fetch_add(&sync[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
