@@ -509,11 +509,11 @@ __global__ void __launch_bounds__(WAVE, 2) k_level_step(KParams P, LevelArgs L)
     march_epilogue(P, threadIdx.x, cfl, nclamp, nbad);
 }
 
-// Workgroup state of the persistent level kernel in LDS: the job counter,
+// Workgroup state of the persistent level kernel in LDS: the pass counter,
 // the barrier's verdict, and each wavefront's Courant number (bit pattern)
 // and counts of the attempt.
 struct LvlShared {
-    int next_job;
+    int next_pass;
     int ok;
     unsigned long long cfl_bits[LVL_WAVES];
     int ncl[LVL_WAVES], nbad[LVL_WAVES];
@@ -535,7 +535,7 @@ struct LvlShared {
 // (measured: one counter for all costs less than counters of 8 or 16
 // workgroups, whose last arrivals wait for a second atomic).  A barrier that does not open within a bounded spin raises
 // the error word and lets the workgroup go on, so every wavefront always
-// reaches the end of the kernel.  Thread 0 also resets the workgroup's job
+// reaches the end of the kernel.  Thread 0 also resets the workgroup's pass
 // counter for the next attempt.  sync words: [1] generation, [2] error,
 // [3] top-level count; counter of group k at word LVL_SYNC_LINE * (k + 1)
 // (one 128-byte line each).
@@ -545,7 +545,7 @@ __device__ __forceinline__ bool level_barrier(uint32_t *sync, unsigned nb, unsig
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        sh.next_job = 0;
+        sh.next_pass = 0;
         unsigned long long m = 0;
         int sc = 0, sb = 0;
 #pragma unroll
@@ -612,7 +612,7 @@ __global__ void __launch_bounds__(WAVE * LVL_WAVES, 2) k_level_persistent(KParam
     swe_ctl *c = P.ctl;
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
     const int nb = gridDim.x, b = blockIdx.x;
-    if (threadIdx.x == 0) sh.next_job = 0;
+    if (threadIdx.x == 0) sh.next_pass = 0;
     __syncthreads();
     swe_ctl_state S = c->s;
     unsigned long long last_bits = 0;
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(WAVE * LVL_WAVES, 2) k_level_persistent(KParam
         int nclamp = 0, nbad = 0;
         for (;;) {
             int k = 0;
-            if (lane == 0) k = atomicAdd(&sh.next_job, 1);
+            if (lane == 0) k = atomicAdd(&sh.next_pass, 1);
             k = __shfl(k, 0, WAVE);
             const long long ps = (long long)k * nb + ((k & 1) ? nb - 1 - b : b);
             if (ps >= L.n_passes) break;
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(WAVE * LVL_WAVES, 2) k_level_persistent(KParam
             sh.ncl[wave] = sc;
             sh.nbad[wave] = sb;
         }
-        // the job counter is read again only after the barrier's closing s_barrier
+        // the pass counter is read again only after the barrier's closing s_barrier
         if (!level_barrier(L.sync, nb, Q.cfl_bits + (size_t)(b % Q.cfl_spread) * Q.cfl_stride, sh)) break;
         last_bits = 0;
         for (int j = 0; j < SWE_CTL_SPREAD; ++j) {

@@ -206,11 +206,9 @@ swe_status swe_level_advance(const swe_level *L, const swe_params *prm, const do
     k.n_nonfinite = &ctl->n_nonfinite;
     swe::LevelArgs la;
     la.n_passes = L->n_passes;
-    la.n_jobs = L->n_jobs;
     la.patches = L->patches;
     la.lanes = (const long long *)L->lanes;
     la.pass_rows = L->pass_rows;
-    la.job_pass = L->job_pass;
     la.sync = L->sync;
     la.pass_row0 = L->pass_row0;
     hipStream_t s = (hipStream_t)stream;
