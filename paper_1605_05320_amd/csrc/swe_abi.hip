@@ -54,20 +54,24 @@ int wave_slots()
 }
 
 // Rows marched per wavefront: ly, and ly + 1 for the first lyr chunks of a
-// strip.  While the launch fits in one wave of resident wavefronts, the most
-// chunks that fit, with at least 2 rows each (a march's time is its rows plus
-// a warm-up of about 2.5 rows, so while the launch fits, shorter marches
-// finish sooner: measured 11.5 us at 2 rows against 24.6 us at 8 rows on a
-// 256^2 grid, 20.0 us at 3 rows against 25.7 us at 8 on 512^2).  Filling the
-// slots puts two wavefronts on every SIMD; with fewer, some SIMDs hold one
-// and finish early while the pairs on the others set the launch's time
-// (measured on 1024^2 with 103 marches of 10 rows per strip: a wavefront
-// alone on its SIMD took 30 us, a pair 30 and 47 us).  Heights differ by at
-// most one row.  While one wave of wavefronts needs marches of at most 56
-// rows it is still the faster choice (2048^2 with waves on every edge: 36
-// rows in one wave 135 us, 24 rows in one and a half waves 151 us; 2560^2:
-// 54-55 rows 205 us, 24 rows 230 us); beyond, marches of 24 rows (measured best
-// of 16 to 138 rows on a 4096^2 grid, and even with 78 rows on 3072^2).
+// strip; heights differ by at most one row.  A march's time is its rows plus
+// a warm-up of about 2.5 rows, and a wavefront alone on its SIMD runs faster
+// than each of a pair (measured on 1024^2 with 103 marches of 10 rows per
+// strip: alone 30 us, a pair 30 and 47 us).  Busy steps, graph replays:
+//  * grids small enough for one-row marches with one wavefront per SIMD take
+//    them (96^2 to 224^2: 7.8-8.5 us against 10.0-10.8 us at 2 rows);
+//  * otherwise the most chunks of at least 2 rows that fill the resident
+//    slots, two wavefronts per SIMD (11.5 us at 2 rows against 24.6 us at 8
+//    on 256^2, 20.0 against 25.7 us at 3 and 8 rows on 512^2) -
+//  * - unless that leaves between one and one and a half wavefronts per SIMD,
+//    where some SIMDs hold pairs that set the launch's time while the others
+//    idle: then one wavefront per SIMD with taller marches (352^2 to 416^2:
+//    13.5-13.9 us at 3 rows against 14.5-15.0 us at 2);
+//  * a launch whose single wave of wavefronts would need marches of more than
+//    56 rows takes marches of 23-24 rows instead, in several waves (2048^2
+//    with waves on every edge: 36 rows in one wave 135 us, 24 rows 151 us;
+//    2560^2: 54-55 rows 205 us, 24 rows 230 us; 24 rows best of 16 to 138 on
+//    4096^2, and equal to 78 rows on 3072^2).
 // SWE_MARCH_ROWS forces ly rows for every chunk (tuning sweeps).
 void march_rows(int nx, int ny, int &ly, int &lyr)
 {
@@ -79,8 +83,15 @@ void march_rows(int nx, int ny, int &ly, int &lyr)
     lyr = 0;
     if (forced > 0) { ly = forced; return; }
     const long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
-    long long c = std::min<long long>(wave_slots() / strips, ny / 2);
-    if (c < 1 || (ny + c - 1) / c > 56) c = (ny + 23) / 24;
+    const long long slots = wave_slots(), simds = slots / 2;
+    long long c;
+    if (strips * ny <= simds) {
+        c = ny;
+    } else {
+        c = std::min<long long>(slots / strips, ny / 2);
+        if (c >= 1 && strips * c > simds && 2 * strips * c < 3 * simds) c = simds / strips;
+        if (c < 1 || (ny + c - 1) / c > 56) c = (ny + 23) / 24;
+    }
     ly = (int)(ny / c);
     lyr = (int)(ny % c);
 }
