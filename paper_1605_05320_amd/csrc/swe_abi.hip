@@ -72,7 +72,8 @@ int wave_slots()
 //    with waves on every edge: 36 rows in one wave 135 us, 24 rows 151 us;
 //    2560^2: 54-55 rows 205 us, 24 rows 230 us; 24 rows best of 16 to 138 on
 //    4096^2, and equal to 78 rows on 3072^2).
-// SWE_MARCH_ROWS forces ly rows for every chunk (tuning sweeps).
+// SWE_MARCH_ROWS forces ly rows for every chunk, SWE_MARCH_CHUNKS the number
+// of balanced chunks per strip (tuning sweeps).
 void march_rows(int nx, int ny, int &ly, int &lyr)
 {
     static const int forced = [] {
@@ -80,12 +81,19 @@ void march_rows(int nx, int ny, int &ly, int &lyr)
         int v = e ? std::atoi(e) : 0;
         return (v >= 1 && v <= 4096) ? v : 0;
     }();
+    static const int forced_chunks = [] {
+        const char *e = std::getenv("SWE_MARCH_CHUNKS");
+        int v = e ? std::atoi(e) : 0;
+        return (v >= 1 && v <= (1 << 20)) ? v : 0;
+    }();
     lyr = 0;
     if (forced > 0) { ly = forced; return; }
     const long long strips = (nx + swe::STRIP - 1) / swe::STRIP;
     const long long slots = wave_slots(), simds = slots / 2;
     long long c;
-    if (strips * ny <= simds) {
+    if (forced_chunks > 0) {
+        c = std::min<long long>(forced_chunks, ny);
+    } else if (strips * ny <= simds) {
         c = ny;
     } else {
         c = std::min<long long>(slots / strips, ny / 2);
