@@ -563,6 +563,28 @@ def test_large_grids_waves_on_every_edge(oracle, S, nx, ny):
     assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
 
 
+@pytest.mark.parametrize("nx,ny", [(224, 224), (288, 288), (384, 384), (416, 400), (60, 1024), (1000, 20),
+                                   (448, 448)])
+def test_launch_regimes_waves_on_every_edge(oracle, S, nx, ny):
+    """The step's launch regimes on waves everywhere: one-row marches with one
+    wavefront per SIMD (224^2, a one-strip 60 x 1024 grid, a 1000 x 20 strip of
+    rows), two-row marches (288^2: 720 wavefronts; 448^2: 1792, pairs on most
+    SIMDs), and one wavefront per SIMD with 2-3-row marches (384^2,
+    416 x 400).  Two steps, every element compared."""
+    O = oracle
+    b = I.basin(nx, 4, ny=ny)
+    go, gs = pair_grids(O, S, nx, ny, b.grid.dx, b.grid.dy)
+    p = O.Params()
+    noise = np.random.default_rng(11).uniform(-0.01, 0.01, b.B.shape)
+    q = O.init_state(go, p, O.NONLINEAR, b.B, b.eta0 + noise)
+    dt = O.dt0(go, p, O.NONLINEAR, b.B, *q)
+    qc, cc = nl_steps_cpu(O, go, p, b.B, q, [dt, 0.9 * dt])
+    qg, cg, _ = nl_steps_gpu(S, gs, S.Params(), b.B, q, [dt, 0.9 * dt])
+    ok, exact = compare_nl(b.B, qg, qc)
+    print(f"{nx}x{ny}: bit-exact={exact}")
+    assert ok and np.allclose(cg, cc, rtol=REL, atol=0)
+
+
 # --------------------------------------------------------------------------
 def _oracle_controlled(O, g, p, B, q, dt, t, t_out, n_attempts, cfl_d, cfl_max):
     """Host mirror of the device-side control rule (same rule as the driver)."""
