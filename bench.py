@@ -662,7 +662,10 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
     nyp = [ny * ratio for (_, _, _, ny) in boxes]
     tab, ncell = S.patch_table(nxp, nyp, [g.dx / ratio] * len(boxes))
     lvl = S.Level(tab, S.SCHED_PACKED)
-    lvl_c = S.Level(tab, S.SCHED_PACKED, chunk_rows=8)
+    # a few small patches fill a fraction of the chip: the autotuner picks
+    # the row chunks (short ones give more, shorter marches)
+    chunks = (1, 2, 4, 8, 16)
+    cands = [lvl] + [S.Level(tab, S.SCHED_PACKED, chunk_rows=r) for r in chunks]
     box_t = torch.tensor(np.array(boxes, np.int32), device=B.device)
     Bp = torch.empty(ncell, **f64)
     qa = [torch.empty(ncell, **f64) for _ in range(3)]
@@ -673,7 +676,7 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
     dt0 = S.Params().cfl_desired / float(spd.view(torch.float64).item())
     init = [x.clone() for x in qa]
 
-    def timed(level):
+    def timed(level, persistent=0):
         for c_ in range(3):
             qa[c_].copy_(init[c_])
         ctl = S.new_ctl()
@@ -681,19 +684,29 @@ def regrid_bench(S, torch, np, g, B, q, flags, f64, ratio=2, n_steps=20):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        S.level_advance(level, S.Params(), Bp, qa, qb, ctl, n_steps, 0)
+        S.level_advance(level, S.Params(), Bp, qa, qb, ctl, n_steps, persistent)
         e1.record()
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), S.read_ctl(ctl)
 
+    wa = [torch.empty(ncell, **f64) for _ in range(3)]
+    wb = [torch.empty(ncell, **f64) for _ in range(3)]
+    ref = [torch.empty(ncell, **f64) for _ in range(3)]
+    mism = torch.zeros(1, dtype=torch.int32, device=B.device)
+    entries, best = S.level_tune(cands, S.Params(), Bp, init, wa, wb, ref, S.new_ctl(), mism, dt0, 10, ncell)
+    lb, pb_, _ = entries[best]
     ms_whole, _ = timed(lvl)
-    ms, c = timed(lvl_c)
+    ms, c = timed(cands[lb], pb_)
     area = sum(nx * ny for (_, _, nx, ny) in boxes)
+    names = ["whole"] + [f"{r}-row-chunks" for r in chunks]
     return {"flagged_cells": int(fl.sum()), "boxes": len(boxes), "box_efficiency": round(int(fl.sum()) / area, 3),
             "cluster_ms": round(t_cluster * 1e3, 3), "refined_cells": ncell, "prolong_us": round(t_prolong * 1e6, 2),
             "level_steps": n_steps, "level_accepted": c.n_accepted,
             "level_us_per_step_whole_patches": round(ms_whole * 1e3 / n_steps, 2),
-            "level_us_per_step": round(ms * 1e3 / n_steps, 2), "level_chunk_rows": 8,
+            "level_candidates_us_per_step": {f"{names[l]}/{'persistent' if pm else 'launch-per-step'}": round(u, 2)
+                                             for l, pm, u in entries if u >= 0},
+            "level_us_per_step": round(ms * 1e3 / n_steps, 2),
+            "level_schedule": f"{names[lb]}/{'persistent' if pb_ else 'launch-per-step'}",
             "level_cell_updates_per_s": ncell * c.n_accepted / (ms * 1e-3)}
 
 
