@@ -799,10 +799,13 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_adj_run1d(Run1dArgs A)
     const int nx = A.P.nx;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1), nwaves = blockDim.x / WAVE;
     const int nstrips = (nx + STRIP - 1) / STRIP;
-    double *q[2][2] = {{lds, lds + nx}, {lds + 2 * nx, lds + 3 * nx}};
+    // plane comp of state buffer b (offsets from lds, so that the accesses
+    // stay LDS accesses: through a table of pointers they became flat ones,
+    // each of which waited for the global stores in flight)
+    auto q = [&](int b, int comp) __attribute__((always_inline)) { return lds + (2 * b + comp) * nx; };
     for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-        q[0][0][k] = A.frames[k];
-        q[0][1][k] = A.frames[A.fplane + k];
+        q(0, 0)[k] = A.frames[k];
+        q(0, 1)[k] = A.frames[A.fplane + k];
     }
     Strip1d st[RUN1D_MAXS];
 #pragma unroll
@@ -820,8 +823,8 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_adj_run1d(Run1dArgs A)
                 const int strip = wave + s * nwaves;
                 if (strip >= nstrips) break;
                 int nbad = 0;
-                (void)step1d_lanes<M>(A.P, strip1d_cell(st[s], q[cur][0], q[cur][1]), lane,
-                                      strip * STRIP + lane - HALO, nu, q[cur ^ 1][0], q[cur ^ 1][1], nbad);
+                (void)step1d_lanes<M>(A.P, strip1d_cell(st[s], q(cur, 0), q(cur, 1)), lane,
+                                      strip * STRIP + lane - HALO, nu, q(cur ^ 1, 0), q(cur ^ 1, 1), nbad);
             }
             __syncthreads();
             cur ^= 1;
@@ -830,8 +833,8 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_adj_run1d(Run1dArgs A)
         // barrier that every thread reaches only after its copy
         double *f = A.frames + (size_t)2 * k * A.fplane;
         for (int i = threadIdx.x; i < nx; i += blockDim.x) {
-            f[i] = q[cur][0][i];
-            f[A.fplane + i] = q[cur][1][i];
+            f[i] = q(cur, 0)[i];
+            f[A.fplane + i] = q(cur, 1)[i];
         }
     }
 }
@@ -850,15 +853,18 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_fwd_run1d(Run1dArgs A)
     const int nx = A.P.nx;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1), nwaves = blockDim.x / WAVE;
     const int nstrips = (nx + STRIP - 1) / STRIP;
-    double *q[2][2] = {{lds, lds + nx}, {lds + 2 * nx, lds + 3 * nx}};
+    // plane comp of state buffer b (offsets from lds, so that the accesses
+    // stay LDS accesses: through a table of pointers they became flat ones,
+    // each of which waited for the global stores in flight)
+    auto q = [&](int b, int comp) __attribute__((always_inline)) { return lds + (2 * b + comp) * nx; };
     unsigned long long *red = (unsigned long long *)(lds + 4 * nx);   // [2][RUN1D_WAVES]
     int *redn = (int *)(red + 2 * RUN1D_WAVES);                        // [2][RUN1D_WAVES]
     swe_ctl *c = A.P.ctl;
     swe_ctl_state S = c->s;
     const double *g0 = S.cur ? A.P.out0 : A.P.in0, *g1 = S.cur ? A.P.out1 : A.P.in1;
     for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-        q[0][0][k] = g0[k];
-        q[0][1][k] = g1[k];
+        q(0, 0)[k] = g0[k];
+        q(0, 1)[k] = g1[k];
     }
     Strip1d st[RUN1D_MAXS];
 #pragma unroll
@@ -877,8 +883,8 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_fwd_run1d(Run1dArgs A)
         for (int s = 0; s < RUN1D_MAXS; ++s) {
             const int strip = wave + s * nwaves;
             if (strip >= nstrips) break;
-            const double cf = step1d_lanes<M>(A.P, strip1d_cell(st[s], q[cur][0], q[cur][1]), lane,
-                                              strip * STRIP + lane - HALO, nu, q[cur ^ 1][0], q[cur ^ 1][1], nbad);
+            const double cf = step1d_lanes<M>(A.P, strip1d_cell(st[s], q(cur, 0), q(cur, 1)), lane,
+                                              strip * STRIP + lane - HALO, nu, q(cur ^ 1, 0), q(cur ^ 1, 1), nbad);
             const unsigned long long b = (unsigned long long)__double_as_longlong(cf);
             bits = b > bits ? b : bits;
         }
@@ -908,8 +914,8 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_fwd_run1d(Run1dArgs A)
             if (A.hist && (S.done || S.n_accepted % A.flag_every == 0)) {
                 double *h = A.hist + (size_t)nrec * 2 * nx;
                 for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-                    h[k] = q[cur][0][k];
-                    h[nx + k] = q[cur][1][k];
+                    h[k] = q(cur, 0)[k];
+                    h[nx + k] = q(cur, 1)[k];
                 }
                 if (threadIdx.x == 0) {
                     A.hist_t[nrec] = S.t;
@@ -929,8 +935,8 @@ __global__ void __launch_bounds__(RUN1D_THREADS) k_fwd_run1d(Run1dArgs A)
     double *o0 = S.cur ? A.P.out0 : const_cast<double *>(A.P.in0);
     double *o1 = S.cur ? A.P.out1 : const_cast<double *>(A.P.in1);
     for (int k = threadIdx.x; k < nx; k += blockDim.x) {
-        o0[k] = q[cur][0][k];
-        o1[k] = q[cur][1][k];
+        o0[k] = q(cur, 0)[k];
+        o1[k] = q(cur, 1)[k];
     }
     if (threadIdx.x == 0) {
         if (any) {
