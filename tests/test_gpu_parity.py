@@ -185,7 +185,10 @@ def test_nl_step_parity_supercritical(oracle, S, mode):
 
 
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("n,ny,seed", [(150, 110, 3), (64, 61, 7)])
+@pytest.mark.parametrize("n,ny,seed", [(150, 110, 3), (64, 61, 7),
+                                       # launch regimes: one-row marches, one wavefront
+                                       # per SIMD, the slots filled
+                                       (224, 224, 9), (384, 384, 5), (1024, 1024, 3)])
 def test_adj_step_parity_2d(oracle, S, n, ny, seed):
     O = oracle
     b = I.basin(n, seed, ny=ny)
@@ -216,6 +219,9 @@ def test_adj_step_parity_2d(oracle, S, n, ny, seed):
     (150, 110, 3, 2, 1, (0, 0, 0, 0)),      # several strips and chunks, ragged tails
     (64, 61, 7, 2, 0, (0, 1, 1, 0)),        # no transverse terms, outflow sides
     (97, 40, 11, 1, 1, (0, 0, 0, 0)),
+    (224, 224, 9, 2, 1, (0, 0, 0, 0)),     # one-row marches
+    (384, 384, 5, 2, 1, (1, 0, 0, 1)),     # one wavefront per SIMD
+    (1024, 600, 2, 2, 1, (0, 0, 0, 0)),    # the slots filled
 ])
 def test_lin2d_step_parity(oracle, S, n, ny, seed, order, trans, bc):
     """2D linear forward (wave form) against the oracle, 8 steps."""
