@@ -184,3 +184,70 @@ def test_persistent_random_levels_match_per_step(oracle, S, seed, n, kind, chunk
     for x, y in zip(res[0][1], res[1][1]):
         assert np.array_equal(x.view(np.int64), y.view(np.int64))
     print(f"seed={seed}: {n} patches, {lvl.c.n_passes} passes, persistent equals per-step")
+
+
+def _shoreline_patch(seed, nx=70, ny=24):
+    """2 m of water west, a thin layer (2..20 mm) draining westward from a dry
+    beach east of column 40: large steps drive some of its cells below zero."""
+    rng = np.random.default_rng(seed)
+    B = np.full((ny, nx), -2.0)
+    B[:, 40:] = 1.0
+    h = np.maximum(0.0, -B)
+    h[:, 30:40] = rng.uniform(0.002, 0.02, (ny, 10))
+    B[:, 30:40] = -h[:, 30:40]
+    hu = np.zeros_like(h)
+    hv = np.zeros_like(h)
+    hu[:, 30:40] = -h[:, 30:40] * rng.uniform(0.5, 3.0, (ny, 10))
+    hv[:, 30:40] = h[:, 30:40] * rng.uniform(-1.0, 1.0, (ny, 10))
+    return B, [h, hu, hv]
+
+
+@pytest.mark.parametrize("kind,chunk", [(1, 0), (1, 8), (0, 5)])
+def test_level_counts_clamps_of_accepted_attempts(oracle, S, kind, chunk):
+    """Three shoreline patches under the level's control rule (desired Courant
+    number 1.2, rejected above 1.25): clamped cells are counted for the
+    accepted attempts only, as the oracle stepping each patch counts them,
+    with the launch per attempt and with the persistent launch (whose
+    workgroups add their wavefronts' counts before one set of atomics); the
+    states equal the oracle's bit for bit."""
+    O = oracle
+    pats = [_shoreline_patch(s) for s in (3, 4, 5)]
+    po = O.Params(cfl_desired=1.2, cfl_max=1.25)
+    grid = O.Grid(70, 24, 10.0, 10.0)
+    q = [list(p[1]) for p in pats]
+    dt, t, acc, rej, ncl_acc, ncl_rej = 4.0, 0.0, 0, 0, 0, 0
+    for _ in range(12):
+        new, cfl, ncl = [], 0.0, 0
+        for (B, _), qk in zip(pats, q):
+            h, hu, hv, c, n = O.swe_step(grid, po, B, *qk, dt)
+            new.append([h, hu, hv])
+            cfl, ncl = max(cfl, c), ncl + n
+        if cfl > po.cfl_max:
+            rej, ncl_rej = rej + 1, ncl_rej + ncl
+            dt = dt * po.cfl_desired / cfl
+        else:
+            acc, ncl_acc = acc + 1, ncl_acc + ncl
+            q, t = new, t + dt
+            if cfl > 0.0:
+                dt = dt * po.cfl_desired / cfl
+    assert rej >= 1 and ncl_acc >= 1 and ncl_rej >= 1
+    tab, ncell = S.patch_table([70] * 3, [24] * 3, [10.0] * 3)
+    lvl = S.Level(tab, kind, chunk_rows=chunk)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    Bd = dev(to_arena([p[0] for p in pats]))
+    ps = S.Params(cfl_desired=1.2, cfl_max=1.25)
+    for persistent in (0, 1):
+        a = [dev(to_arena([p[1][c] for p in pats])) for c in range(3)]
+        b = [torch.full_like(x, float("nan")) for x in a]
+        ctl = S.new_ctl()
+        S.swe_ctl_set(ctl, 0.0, 4.0, 1.0e30, 0)
+        S.level_advance(lvl, ps, Bd, a, b, ctl, 12, persistent)
+        torch.cuda.synchronize()
+        assert int(lvl.sync_t[2].item()) == 0
+        c = S.read_ctl(ctl)
+        assert (c.n_accepted, c.n_rejected, c.t, c.dt) == (acc, rej, t, dt)
+        assert c.n_clamped == ncl_acc and c.n_nonfinite == 0, (persistent, c.n_clamped, ncl_acc)
+        cur = a if c.cur == 0 else b
+        for comp in range(3):
+            assert np.array_equal(cur[comp].cpu().numpy(), to_arena([qk[comp] for qk in q]))
+    print(f"level clamp count: {ncl_acc} (accepted attempts), {ncl_rej} in rejected ones not counted")
