@@ -1,8 +1,9 @@
 """Serving through swe_serve: a scenario's results are identical whether it
 runs alone or in a mix with others in flight; they match the oracle's run;
 admission never exceeds the arena or the slot count; a request larger than
-the arena is refused without blocking the rest; and realtime admission waits
-for each arrival."""
+the arena is refused without blocking the rest; realtime admission waits
+for each arrival; and a request that fails (a non-finite state) leaves the
+others' results as they are alone."""
 import numpy as np
 import pytest
 
@@ -165,3 +166,37 @@ def test_shoreline_thin_layer_scenario_completes(S):
     assert rc == 0 and st[0]["status"] == 0 and st[1]["status"] == 0
     assert st[0]["n_fwd_steps"] > 2000
     assert el < 60.0
+
+
+def test_failing_request_leaves_the_mix_intact(S):
+    """One request of a mix has a NaN in the initial surface of a wet cell:
+    it ends with SWE_E_NONFINITE (the call returns that status), and every
+    other request gives the results it gives alone."""
+    arr = I.arrivals(6, 50.0, 48, 128, seed=7)
+    reqs, alone = [], []
+    for k, a in enumerate(arr):
+        r, b = make_request(S, a.n, a.seed)
+        if k == 2:
+            eta0 = b.eta0.copy()
+            j, i = np.argwhere(b.B < -100.0)[0]
+            eta0[j, i] = np.nan
+            g = S.Grid(b.grid.nx, b.grid.ny, b.grid.dx, b.grid.dy, b.grid.x_lo, b.grid.y_lo)
+            r = S.Request(g, S.Params(), b.B, eta0, (b.target[0], b.target[1], R_TARGET), T0, TS, TF, K, TOL,
+                          flag_every=FLAG_EVERY)
+        else:
+            _, st = S.serve([r], arena_for(S, [r]), 1)
+            assert st[0]["status"] == 0
+            alone.append(outputs(r))
+            r.flag_acc[:] = 0
+            r.maxip_acc[:] = 0
+            for q in r.q:
+                q[:] = 0
+        reqs.append(r)
+    rc, st = S.serve(reqs, arena_for(S, reqs, copies=3), 3, check=False)
+    assert rc == S.E_NONFINITE and st[2]["status"] == S.E_NONFINITE
+    good = [k for k in range(len(reqs)) if k != 2]
+    for k, ref in zip(good, alone):
+        assert st[k]["status"] == 0
+        for x, y in zip(outputs(reqs[k]), ref):
+            assert np.array_equal(x, y)
+    print(f"mix with a failing request: {len(good)} others as alone")
