@@ -251,3 +251,55 @@ def test_level_counts_clamps_of_accepted_attempts(oracle, S, kind, chunk):
         for comp in range(3):
             assert np.array_equal(cur[comp].cpu().numpy(), to_arena([qk[comp] for qk in q]))
     print(f"level clamp count: {ncl_acc} (accepted attempts), {ncl_rej} in rejected ones not counted")
+
+
+def _tuner_setup(S, n=200, seed=4):
+    F64 = dict(dtype=torch.float64, device="cuda")
+    ps = I.patches(n, seed=seed)
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    B = torch.tensor(np.concatenate([x.ravel() for x in ps.B]), **F64)
+    eta = torch.tensor(np.concatenate([x.ravel() for x in ps.eta0]), **F64) * 20.0
+    p = S.Params()
+    init = [torch.empty(ncell, **F64) for _ in range(3)]
+    spd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    for k in range(len(tab)):
+        o, m = tab[k].offset, tab[k].nx * tab[k].ny
+        gk = S.Grid(tab[k].nx, tab[k].ny, tab[k].dx, tab[k].dy)
+        qk = [x[o:o + m] for x in init]
+        S.swe_init(gk, p, B[o:o + m], eta[o:o + m], qk)
+        S.swe_max_speed(gk, p, B[o:o + m], qk, 0, spd)
+    dt0 = p.cfl_desired / float(spd.view(torch.float64).item())
+    work = [[torch.empty(ncell, **F64) for _ in range(3)] for _ in range(3)]
+    return ps, p, B, init, work, ncell, dt0
+
+
+def test_tuner_times_every_candidate_and_picks_the_fastest(S):
+    """swe_level_tune runs every schedule in both launch modes from the same
+    state (row chunks in the persistent mode too), finds every result equal
+    to the first candidate's, and names the fastest."""
+    ps, p, B, init, (wa, wb, ref), ncell, dt0 = _tuner_setup(S)
+    tab, _ = S.patch_table(ps.nx, ps.ny, ps.dx)
+    cands = [S.Level(tab, S.SCHED_STRIP), S.Level(tab, S.SCHED_PACKED)] + \
+        [S.Level(tab, S.SCHED_PACKED, chunk_rows=r) for r in (1, 8, 16)]
+    mism = torch.zeros(1, dtype=torch.int32, device="cuda")
+    entries, best = S.level_tune(cands, p, B, init, wa, wb, ref, S.new_ctl(), mism, dt0, 5, ncell)
+    assert sorted((l, pm) for l, pm, _ in entries) == [(l, pm) for l in range(len(cands)) for pm in (0, 1)]
+    assert all(u > 0.0 for _, _, u in entries)
+    assert entries[best][2] == min(u for _, _, u in entries)
+    assert int(mism.item()) == 0
+    print("tuner:", {f"{l}/{pm}": round(u, 1) for l, pm, u in entries}, "best", entries[best][:2])
+
+
+def test_tuner_rejects_candidates_that_disagree(S):
+    """Two 'schedules' of different levels (walls against extrapolating
+    sides) give different states: the tuner reports it (SWE_E_HIP) instead of
+    timing them."""
+    ps, p, B, init, (wa, wb, ref), ncell, dt0 = _tuner_setup(S, n=40, seed=6)
+    walls, _ = S.patch_table(ps.nx, ps.ny, ps.dx)
+    open_, _ = S.patch_table(ps.nx, ps.ny, ps.dx, bc=(S.BC_EXTRAP,) * 4)
+    cands = [S.Level(walls, S.SCHED_PACKED), S.Level(open_, S.SCHED_PACKED)]
+    mism = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(S.SweError) as ei:
+        S.level_tune(cands, p, B, init, wa, wb, ref, S.new_ctl(), mism, dt0, 5, ncell)
+    assert ei.value.status == S.E_HIP
+    assert int(mism.item()) > 0
