@@ -657,3 +657,91 @@ def test_device_controlled_steps_match_oracle(oracle, S):
     ok, exact = compare_nl(b.B, [host(x) for x in cur], qc2)
     print(f"controlled: {c.n_accepted} accepted, {c.n_rejected} rejected, bit-exact={exact}")
     assert ok
+
+
+def _oracle_controlled_flagged(O, g, p, B, q, dt, t, t_out, n_attempts, cfl_d, cfl_max, fl):
+    """_oracle_controlled with the driver's flag pass after each accepted
+    attempt that reaches t_out or brings the accepted count to a multiple of
+    flag_every (Sec. 4.2 window at the new time)."""
+    frames, K, every, t0, ts, tf, tol = fl
+    shp = (g.ny, g.nx)
+    acc_f, macc = np.zeros(shp, np.int8), np.zeros(shp)
+    final, n_calls = None, 0
+    fin = False
+    if dt >= t_out - t:
+        dt, fin = t_out - t, True
+    done, acc, rej = False, 0, 0
+    for _ in range(n_attempts):
+        if done:
+            continue
+        h, hu, hv, cfl, _ = O.swe_step(g, p, B, *q, dt)
+        if cfl > cfl_max:
+            rej += 1
+            dt = dt * cfl_d / cfl
+        else:
+            acc += 1
+            q = [h, hu, hv]
+            t = t_out if fin else t + dt
+            done = fin
+            if cfl > 0.0:
+                dt = dt * cfl_d / cfl
+            if done or acc % every == 0:
+                w = O.window(t, t0, ts, tf, K)
+                lo, hi = (1, 0) if w is None else w
+                f, m = O.flag(g, p, O.NONLINEAR, B, *q, frames, K, lo, hi, tol, acc_f, macc)
+                n_calls += 1
+                if done:
+                    final = (f, m)
+        if not done:
+            fin = False
+            if dt >= t_out - t:
+                dt, fin = t_out - t, True
+    return q, t, acc, rej, done, acc_f, macc, final, n_calls
+
+
+@pytest.mark.parametrize("every,tf_dt0", [(1, 24.0), (3, 27.0)])
+def test_advance_flagged_matches_oracle(oracle, S, every, tf_dt0):
+    """swe_advance_flagged: the flag passes the device decides on (cadence of
+    flag_every accepted attempts, the attempt reaching t_out, none after a
+    rejection or once done) and the window each uses, against the host mirror
+    of the same rule; accumulators, final flags and the pass count."""
+    O = oracle
+    n, K = 120, 8
+    b = I.basin(n, 12)
+    go, gs = pair_grids(O, S, n, n, b.grid.dx, b.grid.dy)
+    po = O.Params(cfl_desired=0.9, cfl_max=0.95)
+    ps = S.Params(cfl_desired=0.9, cfl_max=0.95)
+    q = O.init_state(go, po, O.NONLINEAR, b.B, b.eta0 * 30.0)
+    dt0 = O.dt0(go, po, O.NONLINEAR, b.B, *q)
+    # tf below t_out: the last passes have empty windows (flags_final all 0)
+    t_out, tf, ts = 25.3 * dt0, tf_dt0 * dt0, 9.0 * dt0
+    rng = np.random.default_rng(31)
+    frames = rng.normal(0.0, 1.0, (K + 1, 3, n, n)) * np.array([1e-2, 1e-3, 1e-3])[None, :, None, None]
+    tol = 2e-2
+    fl = (frames, K, every, 0.0, ts, tf, tol)
+    qc, t_c, acc_c, rej_c, done_c, facc_c, macc_c, final_c, calls_c = _oracle_controlled_flagged(
+        O, go, po, b.B, q, 1.3 * dt0, 0.0, t_out, 40, 0.9, 0.95, fl)
+    assert rej_c >= 1 and done_c and final_c is not None
+    assert facc_c.any() and not facc_c.all()
+    assert final_c[0].any() == (tf > t_out)
+    Bd = dev(b.B)
+    a = [dev(x) for x in q]
+    bb = [torch.empty_like(x) for x in a]
+    ctl = S.new_ctl()
+    fin_g = torch.full((n, n), 7, dtype=torch.int8, device=DEV)
+    facc_g = torch.zeros(n, n, dtype=torch.int8, device=DEV)
+    macc_g = torch.zeros(n, n, dtype=torch.float64, device=DEV)
+    S.swe_ctl_set(ctl, 0.0, 1.3 * dt0, t_out, 0)
+    S.swe_advance_flagged(gs, ps, Bd, a, bb, ctl, 40, dev(frames), K, every, 0.0, ts, tf, tol,
+                          flags_final=fin_g, flag_acc=facc_g, maxip_acc=macc_g)
+    c = S.read_ctl(ctl)
+    assert (c.n_accepted, c.n_rejected, c.done, c.t) == (acc_c, rej_c, 1, t_c)
+    assert c.n_flag_calls == calls_c
+    cur = a if c.cur == 0 else bb
+    ok, exact = compare_nl(b.B, [host(x) for x in cur], qc)
+    assert ok
+    assert close(host(macc_g), macc_c)
+    assert _flags_match(host(facc_g), facc_c, macc_c, tol)
+    assert _flags_match(host(fin_g), final_c[0], final_c[1], tol)
+    print(f"advance_flagged every={every}: {calls_c} flag passes, {int(facc_c.sum())} flagged, "
+          f"bit-exact state={exact}, maxip={np.array_equal(host(macc_g), macc_c)}")
