@@ -196,3 +196,51 @@ def test_static_driver_refuses_a_problem_beyond_its_array(S):
         S.swe_run_static(pb, stream=null_stream)
     assert ei.value.status == S.E_NOMEM
     assert "static workspace" in str(ei.value)
+
+
+@pytest.mark.parametrize("case,grid,msg", [
+    ("empty x", dict(nx=0, ny=8), "nx = 0"),
+    ("one column", dict(nx=1, ny=8), "nx = 1"),
+    ("empty y", dict(nx=8, ny=0), "ny = 0"),
+    ("pitch below nx", dict(nx=8, ny=8, pitch=7), "pitch"),
+    ("row beyond the store range", dict(nx=(1 << 27) + 1, ny=2), "nx ="),
+    ("zero dx", dict(nx=8, ny=8, dx=0.0), "dx"),
+    ("NaN dx", dict(nx=8, ny=8, dx=float("nan")), "dx"),
+    ("zero dy", dict(nx=8, ny=8, dy=0.0), "dy"),
+    ("unknown boundary", dict(nx=8, ny=8, bc=(0, 0, 2, 0)), "bc[2]"),
+])
+def test_degenerate_grids_are_refused_before_touching_the_device(S, case, grid, msg):
+    """Empty and one-column grids, a pitch below nx, a row too long for the
+    kernels' 32-bit row offsets, non-positive or NaN cell sizes and unknown
+    boundary codes are argument errors of every entry point that takes a grid;
+    the check comes first, so host buffers stand in for the planes."""
+    import torch
+    kw = dict(dx=100.0, dy=100.0)
+    kw.update(grid)
+    g = S.Grid(**kw)
+    B = torch.zeros(64, dtype=torch.float64)
+    qa = [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    qb = [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    null_stream = type("NullStream", (), {"cuda_stream": 0})()
+    for fn, prm in ((S.swe_step, S.Params()), (S.adj_step, S.Params())):
+        with pytest.raises(S.SweError) as e:
+            fn(g, prm, B, qa, qb, 0.1, stream=null_stream)
+        assert e.value.status == S.E_INVAL, case
+        assert msg in S.lib().swe_last_error().decode(), case
+
+
+@pytest.mark.parametrize("case", ["zero dt", "negative dt", "NaN dt", "aliased planes", "nonlinear in 1D"])
+def test_step_refuses_degenerate_calls(S, case):
+    """A step of non-positive or NaN length, output planes that alias the
+    inputs, and the (two-dimensional) nonlinear model on a single row are
+    refused with SWE_E_INVAL before any device work."""
+    import torch
+    g = S.Grid(8, 1 if case == "nonlinear in 1D" else 8, 100.0, 100.0)
+    B = torch.zeros(64, dtype=torch.float64)
+    qa = [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    qb = qa if case == "aliased planes" else [torch.zeros(64, dtype=torch.float64) for _ in range(3)]
+    dt = {"zero dt": 0.0, "negative dt": -1.0, "NaN dt": float("nan")}.get(case, 0.1)
+    null_stream = type("NullStream", (), {"cuda_stream": 0})()
+    with pytest.raises(S.SweError) as e:
+        S.swe_step(g, S.Params(), B, qa, qb, dt, stream=null_stream)
+    assert e.value.status == S.E_INVAL
