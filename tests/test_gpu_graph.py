@@ -1,6 +1,7 @@
 """HIP-graph capture of the device-controlled stepping (the form the headline
-step is timed in) and of a batched level's advance (launch per attempt, and
-the one persistent launch): a graph of
+step is timed in), of the same with device-scheduled flag passes, and of a
+batched level's advance (launch per attempt, and the one persistent launch):
+a graph of
 K attempts, captured once, is replayed several times with eager work and
 synchronisations in between, and the state and control block after every
 replay equal, bit for bit, those of the same attempts issued eagerly."""
@@ -117,3 +118,55 @@ def test_level_graph_replays_match_eager(S, persistent):
                   lambda st: S.level_advance(lv, p, B, ga, gb, ctl_g, 5, persistent, stream=st),
                   ctl_e, ctl_g, ea, eb, ga, gb)
     assert int(lv.sync_t[2].item()) == 0
+
+
+def test_advance_flagged_graph_replays_match_eager(S):
+    """swe_advance_flagged captured once (7 attempts, a flag pass after every
+    second accepted one, decided on the device from the control block): every
+    replay leaves the state, control block and flag accumulators equal to
+    those of the same attempts issued eagerly."""
+    n, ny, K = 200, 150, 6
+    b = I.basin(n, 3, ny=ny)
+    g = S.Grid(n, ny, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **F64)
+    q0 = [torch.empty(ny, n, **F64) for _ in range(3)]
+    S.swe_init(g, p, B, torch.tensor(b.eta0 * 20.0, **F64), q0)
+    spd = torch.zeros(1, dtype=torch.int64, device="cuda")
+    S.swe_max_speed(g, p, B, q0, 0, spd)
+    dt0 = p.cfl_desired / float(spd.view(torch.float64).item())
+    rng = np.random.default_rng(8)
+    frames = torch.tensor(rng.normal(0.0, 1e-2, (K + 1, 3, ny, n)), **F64)
+    t0, ts, tf, tol = 0.0, 10.0 * dt0, 40.0 * dt0, 1e-2
+    bufs = {}
+    for side in ("e", "g"):
+        bufs[side] = dict(a=[x.clone() for x in q0], b=[torch.empty_like(x) for x in q0], ctl=S.new_ctl(),
+                          acc=torch.zeros(ny, n, dtype=torch.int8, device="cuda"),
+                          macc=torch.zeros(ny, n, **F64))
+        S.swe_ctl_set(bufs[side]["ctl"], 0.0, dt0, 1.0e30, 0)
+    torch.cuda.synchronize()
+
+    def run(side, stream=None):
+        d = bufs[side]
+        S.swe_advance_flagged(g, p, B, d["a"], d["b"], d["ctl"], 7, frames, K, 2, t0, ts, tf, tol,
+                              flag_acc=d["acc"], maxip_acc=d["macc"], stream=stream)
+
+    graph = capture(lambda st: run("g", st))
+    scratch = torch.randn(1 << 16, **F64)
+    for r in range(3):
+        run("e")
+        torch.cuda.synchronize()
+        want_q, want_c = current(S, bufs["e"]["ctl"], bufs["e"]["a"], bufs["e"]["b"])
+        graph.replay()
+        scratch.mul_(1.0001).add_(float(r))
+        torch.cuda.synchronize()
+        got_q, got_c = current(S, bufs["g"]["ctl"], bufs["g"]["a"], bufs["g"]["b"])
+        calls = (S.read_ctl(bufs["g"]["ctl"]).n_flag_calls, S.read_ctl(bufs["e"]["ctl"]).n_flag_calls)
+        print(f"replay {r}: t = {got_c[0]:.3f}, accepted {got_c[2]}, flag passes {calls[0]}, "
+              f"flagged {int(bufs['g']['acc'].sum().item())}")
+        assert got_c == want_c and calls[0] == calls[1], r
+        for x, y in zip(got_q, want_q):
+            assert np.array_equal(x, y), r
+        assert torch.equal(bufs["g"]["acc"], bufs["e"]["acc"]), r
+        assert torch.equal(bufs["g"]["macc"], bufs["e"]["macc"]), r
+    assert calls[0] >= 6 and bufs["g"]["acc"].any()
