@@ -340,7 +340,8 @@ typedef struct {
  * Courant number the max over all patches).  persistent = 0: one launch per
  * attempt, one wavefront per pass (graph-capturable).  persistent = 1: a
  * single cooperative launch of at most one wavefront per resident slot, in
- * workgroups of 8, runs all attempts, the workgroups meeting at a grid
+ * workgroups of 8 (one per pass in eight, but at least one per CU while
+ * there are passes for them), runs all attempts, the workgroups meeting at a grid
  * barrier after each attempt;
  * a barrier that does not open within a bounded spin sets sync[2] to nonzero
  * and the launch ends early (the caller checks sync[2]; the state is then
