@@ -251,7 +251,8 @@ def test_lin2d_step_parity(oracle, S, n, ny, seed, order, trans, bc):
         assert close(x, y)
 
 
-@pytest.mark.parametrize("n,order", [(2000, 2), (333, 2), (61, 1)])
+# 1000003 cells: 16667 strips of the 1D step, the last one ragged
+@pytest.mark.parametrize("n,order", [(2000, 2), (333, 2), (61, 1), (1000003, 2)])
 def test_1d_parity(oracle, S, n, order):
     O = oracle
     s = I.shelf1d(n, seed=4)
