@@ -365,8 +365,10 @@ typedef struct {
 /*
  * swe_level_tune - autotuner of the batched level: for every candidate level
  * schedule (levels[k], e.g. SWE_SCHED_STRIP and SWE_SCHED_PACKED of the same
- * patches) and both launch modes, copy the state `init` into `work_a`, run
- * n_trial attempts from dt with the control rule, time them with HIP events,
+ * patches) and both launch modes, run one untimed attempt from `init` (so
+ * that one-time costs of the launch form are not timed), copy the state
+ * `init` into `work_a`, run n_trial attempts from dt with the control rule,
+ * time them with HIP events,
  * and compare the resulting state bit for bit with the first candidate's (kept
  * in `ref`).  Writes 2*n_levels entries to `out` (host) and the index of the
  * fastest into *best.  Returns SWE_E_HIP if two candidates disagree in any
