@@ -169,6 +169,8 @@ def main():
                     help="run the 1D shelf problem (2000 cells, 3 h, 60 snapshots) K times and exit")
     ap.add_argument("--run1d-per-step", type=int, default=0, choices=(0, 1),
                     help="with --run1d-only: 1 launches every step (launch_per_step)")
+    ap.add_argument("--level-only", action="store_true",
+                    help="run the batched-level leg (3000 patches, 100 steps, tuner, baselines) and exit")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
                     help="launch the --n step with waves on every edge K times and exit (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -226,6 +228,9 @@ def main():
         times = [round(run1d_shelf(S, torch, I, np, f64, launch_per_step=args.run1d_per_step), 4)
                  for _ in range(args.run1d_only)]
         print(json.dumps({"run1d_s": times, "launch_per_step": args.run1d_per_step}), flush=True)
+        return
+    if args.level_only:
+        print(json.dumps({"level": level_bench(S, torch, I, np, f64)}), flush=True)
         return
     if args.busy_only > 0:
         g, p, B, qa, qb, dt = busy_state(S, torch, I, np, f64, args.n)
