@@ -169,6 +169,8 @@ def main():
                     help="run the 1D shelf problem (2000 cells, 3 h, 60 snapshots) K times and exit")
     ap.add_argument("--run1d-per-step", type=int, default=0, choices=(0, 1),
                     help="with --run1d-only: 1 launches every step (launch_per_step)")
+    ap.add_argument("--run2d-only", type=int, default=0, metavar="K",
+                    help="run the 512^2 adjoint-flagged problem (64 snapshots, flags every step) K times and exit")
     ap.add_argument("--level-only", action="store_true",
                     help="run the batched-level leg (3000 patches, 100 steps, tuner, baselines) and exit")
     ap.add_argument("--busy-only", type=int, default=0, metavar="K",
@@ -228,6 +230,10 @@ def main():
         times = [round(run1d_shelf(S, torch, I, np, f64, launch_per_step=args.run1d_per_step), 4)
                  for _ in range(args.run1d_only)]
         print(json.dumps({"run1d_s": times, "launch_per_step": args.run1d_per_step}), flush=True)
+        return
+    if args.run2d_only > 0:
+        print(json.dumps({"run2d_512_s": [round(run2d_512(S, torch, I, f64), 4) for _ in range(args.run2d_only)]}),
+              flush=True)
         return
     if args.level_only:
         print(json.dumps({"level": level_bench(S, torch, I, np, f64)}), flush=True)
@@ -513,6 +519,29 @@ def run1d_shelf(S, torch, I, np, f64, launch_per_step=0):
     macc = torch.zeros(1, n, **f64)
     pb = S.make_problem(g, S.Params(model=S.LINEAR), B, E, s1.target, 0.0, 0.0, tf, K, tol, frames, q, None, acc,
                         macc, launch_per_step=launch_per_step)
+    ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    S.swe_run(pb, ws)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t
+
+
+def run2d_512(S, torch, I, f64):
+    """One swe_run of the adjoint-flagging workload of run_bench (512^2 basin,
+    64 snapshots, window [3600 s, 7200 s], tol 1e-4, flags every step);
+    returns its wall time."""
+    n, K = 512, 64
+    b = I.basin(n, 3)
+    g = S.Grid(n, n, b.grid.dx, b.grid.dy)
+    prm = S.Params()
+    B = torch.tensor(b.B, **f64)
+    E = torch.tensor(b.eta0, **f64)
+    frames = torch.zeros(K + 1, 3, n, n, **f64)
+    q = [torch.zeros(n, n, **f64) for _ in range(3)]
+    acc = torch.zeros(n, n, dtype=torch.int8, device=B.device)
+    macc = torch.zeros(n, n, **f64)
+    pb = S.make_problem(g, prm, B, E, b.target, 0.0, 3600.0, 7200.0, K, 1e-4, frames, q, None, acc, macc)
     ws = torch.empty(S.swe_run_workspace_bytes(pb) // 8 + 64, **f64)
     torch.cuda.synchronize()
     t = time.perf_counter()
