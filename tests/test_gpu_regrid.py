@@ -86,3 +86,35 @@ def test_flags_to_patches_to_level(oracle, S):
             scale = np.abs(rk).max() + (1.0 if comp == 0 else 0.0)
             assert np.abs(gk - rk).max() <= 1e-12 * max(scale, 1e-300), (k, comp)
         off += m
+
+
+@pytest.mark.parametrize("ratio", [1, 3, 4, 6])
+def test_prolong_ratios_match_oracle(S, ratio):
+    """Injection at other refinement ratios (the paper's nested levels refine
+    by 5 and 6, Sec. 6), for boxes of assorted shapes including ones on the
+    grid's edges and corner, bit for bit against the oracle's repetition."""
+    rng = np.random.default_rng(40 + ratio)
+    nx, ny = 70, 45
+    fields = [rng.normal(0.0, 1.0, (ny, nx)) for _ in range(4)]
+    boxes = [(0, 0, 5, 7), (nx - 3, ny - 2, 3, 2), (11, 20, 17, 1), (30, 0, 1, ny), (20, 10, 13, 9)]
+    nxp = [w * ratio for (_, _, w, _) in boxes]
+    nyp = [h * ratio for (_, _, _, h) in boxes]
+    tab, ncell = S.patch_table(nxp, nyp, [1.0] * len(boxes))
+    # the device patch table alone (at ratio 1 some patches are one cell
+    # wide, which injection allows and a level schedule does not)
+    patches_t = dev(np.frombuffer(bytes(tab), dtype=np.uint8), torch.uint8)
+    gs = S.Grid(nx, ny, 1.0, 1.0)
+    out_B = torch.full((ncell,), float("nan"), dtype=torch.float64, device="cuda")
+    out_q = [torch.full((ncell,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(3)]
+    box_t = dev(np.array(boxes, np.int32), torch.int32)
+    S.prolong(gs, dev(fields[3]), [dev(x) for x in fields[:3]], box_t, patches_t, len(boxes), ratio,
+              out_B, out_q)
+    ref = R.prolong(fields, boxes, ratio)
+    got = [x.cpu().numpy() for x in (out_q[0], out_q[1], out_q[2], out_B)]
+    off = 0
+    for k, parts in enumerate(ref):
+        m = nxp[k] * nyp[k]
+        for c in range(4):
+            assert np.array_equal(got[c][off:off + m].reshape(nyp[k], nxp[k]), parts[c]), (k, c)
+        off += m
+    assert off == ncell
