@@ -19,8 +19,9 @@ def S():
     return swe
 
 
-def oracle_level(O, ps, B, q, dt, n_steps, cfl_d=0.9, cfl_max=1.0, t_out=1e30):
-    """Host mirror of the control rule with the Courant number of the level."""
+def oracle_level(O, ps, B, q, dt, n_steps, cfl_d=0.9, cfl_max=1.0, t_out=1e30, bcs=None):
+    """Host mirror of the control rule with the Courant number of the level
+    (bcs: each patch's four boundary codes, walls if not given)."""
     p = O.Params(cfl_desired=cfl_d, cfl_max=cfl_max)
     t, fin, acc, rej = 0.0, False, 0, 0
     if dt >= t_out - t:
@@ -28,7 +29,8 @@ def oracle_level(O, ps, B, q, dt, n_steps, cfl_d=0.9, cfl_max=1.0, t_out=1e30):
     for _ in range(n_steps):
         new, cfl = [], 0.0
         for k in range(len(ps.nx)):
-            g = O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k])
+            g = O.Grid(int(ps.nx[k]), int(ps.ny[k]), ps.dx[k], ps.dx[k], 0.0, 0.0,
+                       (0, 0, 0, 0) if bcs is None else tuple(bcs[k]))
             h, hu, hv, c, _ = O.swe_step(g, p, B[k], *q[k], dt)
             new.append([h, hu, hv])
             cfl = max(cfl, c)
@@ -115,6 +117,50 @@ def test_level_parity(oracle, S, setup, kind, persistent, chunk):
             exact &= np.array_equal(got[comp][off:off + n], qc[k][comp].ravel())
         off += n
     print(f"level kind={kind} persistent={persistent} chunk={chunk}: bit-exact={exact}")
+
+
+@pytest.mark.parametrize("persistent,chunk", [(0, 0), (1, 16), (0, 3)])
+def test_level_parity_mixed_boundaries(oracle, S, setup, persistent, chunk):
+    """Each patch with its own mix of walls and extrapolating sides (the
+    level keeps them per lane as one bit word), against the oracle stepping
+    each patch with its own boundary conditions."""
+    ps, B, q, dt0 = setup
+    rng = np.random.default_rng(17)
+    bcs = [tuple(int(v) for v in rng.integers(0, 2, 4)) for _ in range(len(ps.nx))]
+    assert len(set(bcs)) > 4
+    n_steps = 5
+    qc, t, dt, acc, rej = oracle_level(oracle, ps, B, q, 1.6 * dt0, n_steps, bcs=bcs)
+    assert rej >= 1 and acc >= 1
+    tab, ncell = S.patch_table(ps.nx, ps.ny, ps.dx)
+    for k, bc in enumerate(bcs):
+        for side in range(4):
+            tab[k].bc[side] = bc[side]
+    lvl = S.Level(tab, S.SCHED_PACKED, chunk_rows=chunk)
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    Bd = dev(to_arena(B))
+    a = [dev(to_arena([qq[c] for qq in q])) for c in range(3)]
+    b = [torch.full_like(x, float("nan")) for x in a]
+    ctl = S.new_ctl()
+    S.swe_ctl_set(ctl, 0.0, 1.6 * dt0, 1e30, 0)
+    S.level_advance(lvl, S.Params(), Bd, a, b, ctl, n_steps, persistent)
+    torch.cuda.synchronize()
+    assert int(lvl.sync_t[2].item()) == 0
+    c = S.read_ctl(ctl)
+    assert (c.n_accepted, c.n_rejected, c.t, c.dt) == (acc, rej, t, dt)
+    got = [x.cpu().numpy() for x in (a if c.cur == 0 else b)]
+    off, exact = 0, True
+    for k in range(len(ps.nx)):
+        n = int(ps.nx[k]) * int(ps.ny[k])
+        for comp in range(3):
+            g_ = got[comp][off:off + n].reshape(qc[k][comp].shape)
+            r_ = qc[k][comp]
+            if comp == 0:
+                g_, r_ = g_ + B[k], r_ + B[k]
+            scale = np.abs(r_).max() + (1.0 if comp == 0 else 0.0)
+            assert np.abs(g_ - r_).max() <= 1e-12 * max(scale, 1e-300), (k, comp, bcs[k])
+            exact &= np.array_equal(got[comp][off:off + n], qc[k][comp].ravel())
+        off += n
+    print(f"level mixed boundaries persistent={persistent} chunk={chunk}: bit-exact={exact}")
 
 
 @pytest.mark.parametrize("chunk", [2, 5])
