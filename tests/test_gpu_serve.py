@@ -1,5 +1,6 @@
 """Serving through swe_serve: a scenario's results are identical whether it
-runs alone or in a mix with others in flight; they match the oracle's run;
+runs alone or in a mix with others in flight; they match the oracle's run (a 1D request beside 2D
+ones too);
 admission never exceeds the arena or the slot count; a request larger than
 the arena is refused without blocking the rest; realtime admission waits
 for each arrival; and a request that fails (a non-finite state) leaves the
@@ -200,3 +201,44 @@ def test_failing_request_leaves_the_mix_intact(S):
         for x, y in zip(outputs(reqs[k]), ref):
             assert np.array_equal(x, y)
     print(f"mix with a failing request: {len(good)} others as alone")
+
+
+def test_served_1d_request_beside_2d_matches_oracle(oracle, S):
+    """A one-dimensional request (the 2000-cell shelf, linear model, 20
+    snapshots over an hour) served beside two 2D basins: its results match
+    the oracle's run, and the 2D requests give the results they give alone."""
+    O = oracle
+    n, K1, tf1, tol1 = 2000, 20, 3600.0, 1e-3
+    s = I.shelf1d(n, seed=0)
+    g1 = S.Grid(n, 1, s.dx, 1.0, s.x_lo)
+    r1d = S.Request(g1, S.Params(model=S.LINEAR), s.B.reshape(1, n), s.eta0.reshape(1, n), s.target,
+                    0.0, 0.0, tf1, K1, tol1)
+    twod = [make_request(S, 64, 1010)[0], make_request(S, 96, 1011)[0]]
+    alone = []
+    for r in twod:
+        _, st = S.serve([r], arena_for(S, [r]), 1)
+        assert st[0]["status"] == 0
+        alone.append(outputs(r))
+        r.flag_acc[:] = 0
+        r.maxip_acc[:] = 0
+        for q in r.q:
+            q[:] = 0
+    reqs = [twod[0], r1d, twod[1]]
+    rc_, st = S.serve(reqs, arena_for(S, reqs, copies=3), 3)
+    assert all(x["status"] == 0 for x in st)
+    for r, ref in zip(twod, alone):
+        for x, y in zip(outputs(r), ref):
+            assert np.array_equal(x, y)
+    go = O.Grid(n, 1, s.dx, 1.0, s.x_lo, 0.0, (0, 0, 0, 0))
+    rc = O.run(go, O.Params(), O.LINEAR, s.B, s.eta0, s.target, 0.0, 0.0, tf1, K1, tol1)
+    assert st[1]["n_fwd_steps"] == rc.n_fwd_steps and st[1]["n_adj_steps"] == rc.n_adj_steps
+    for c in (0, 1):
+        ref = rc.q[c].ravel()
+        assert np.abs(r1d.q[c].ravel() - ref).max() <= REL * np.abs(ref).max()
+    macc = rc.maxip_acc.ravel()
+    assert np.abs(r1d.maxip_acc.ravel() - macc).max() <= REL * np.abs(macc).max()
+    band = np.abs(macc - tol1) <= 1e-12 * tol1
+    assert np.array_equal(r1d.flag_acc.ravel()[~band], rc.flag_acc.ravel()[~band])
+    assert rc.flag_acc.any()
+    print(f"served 1D beside 2D: {st[1]['n_fwd_steps']} forward steps, "
+          f"bit-exact={all(np.array_equal(r1d.q[c].ravel(), rc.q[c].ravel()) for c in (0, 1))}")
