@@ -1,7 +1,7 @@
 """Serving through swe_serve: a scenario's results are identical whether it
-runs alone or in a mix with others in flight; they match the oracle's run (a 1D request beside 2D
-ones too);
-admission never exceeds the arena or the slot count; a request larger than
+runs alone or in a mix with others in flight; they match the oracle's run
+(a 1D request beside 2D ones too); admission never exceeds the arena or the
+slot count; a request larger than
 the arena is refused without blocking the rest; realtime admission waits
 for each arrival; and a request that fails (a non-finite state) leaves the
 others' results as they are alone."""
