@@ -746,3 +746,39 @@ def test_advance_flagged_matches_oracle(oracle, S, every, tf_dt0):
     assert _flags_match(host(fin_g), final_c[0], final_c[1], tol)
     print(f"advance_flagged every={every}: {calls_c} flag passes, {int(facc_c.sum())} flagged, "
           f"bit-exact state={exact}, maxip={np.array_equal(host(macc_g), macc_c)}")
+
+
+def test_flag_parity_pitched_rows(oracle, S):
+    """The flag pass on a grid whose rows are padded (pitch > nx) for the
+    state, the snapshots and every output plane: the padding is neither read
+    into the result nor written, and the cells match the unpadded oracle."""
+    O = oracle
+    rng = np.random.default_rng(12)
+    nx, ny, K, pitch = 131, 77, 6, 131 + 13
+    B = -rng.uniform(-20.0, 300.0, (ny, nx))
+    q0 = np.maximum(0.0, rng.normal(0, 0.3, (ny, nx)) - B)
+    q1, q2 = rng.normal(0, 1, (ny, nx)), rng.normal(0, 1, (ny, nx))
+    frames = rng.normal(0, 1e-3, (K + 1, 3, ny, nx))
+    tol = 2e-3
+    go = O.Grid(nx, ny, 100.0, 100.0, 0.0, 0.0, (0, 0, 0, 0))
+    gs = S.Grid(nx, ny, 100.0, 100.0, 0.0, 0.0, (0, 0, 0, 0), pitch)
+
+    def padded(a, fill=np.nan):
+        out = np.full(a.shape[:-1] + (pitch,), fill)
+        out[..., :nx] = a
+        return dev(out)
+    Bd, fd = padded(B), padded(frames)
+    qd = [padded(q0), padded(q1), padded(q2)]
+    acc_c, macc_c = np.zeros((ny, nx), np.int8), np.zeros((ny, nx))
+    acc_g = torch.zeros(ny, pitch, dtype=torch.int8, device=DEV)
+    macc_g = torch.zeros(ny, pitch, dtype=torch.float64, device=DEV)
+    for (lo, hi) in [(0, K), (2, 4)]:
+        fl_c, m_c = O.flag(go, O.Params(), O.NONLINEAR, B, q0, q1, q2, frames, K, lo, hi, tol, acc_c, macc_c)
+        fl_g = torch.full((ny, pitch), 5, dtype=torch.int8, device=DEV)
+        m_g = torch.full((ny, pitch), -1.0, dtype=torch.float64, device=DEV)
+        S.adj_flag(gs, S.Params(), Bd, qd, fd, K, lo, hi, tol, fl_g, m_g, acc_g, macc_g)
+        fg, mg = host(fl_g), host(m_g)
+        assert np.array_equal(fg[:, :nx], fl_c) and np.array_equal(mg[:, :nx], m_c)
+        assert (fg[:, nx:] == 5).all() and (mg[:, nx:] == -1.0).all()
+    assert np.array_equal(host(acc_g)[:, :nx], acc_c) and np.array_equal(host(macc_g)[:, :nx], macc_c)
+    assert not host(acc_g)[:, nx:].any() and not host(macc_g)[:, nx:].any()
