@@ -782,3 +782,41 @@ def test_flag_parity_pitched_rows(oracle, S):
         assert (fg[:, nx:] == 5).all() and (mg[:, nx:] == -1.0).all()
     assert np.array_equal(host(acc_g)[:, :nx], acc_c) and np.array_equal(host(macc_g)[:, :nx], macc_c)
     assert not host(acc_g)[:, nx:].any() and not host(macc_g)[:, nx:].any()
+
+
+def test_adj_step_pitched_rows(oracle, S):
+    """The adjoint step on rows padded to a pitch above nx (NaN in the
+    padding of every input plane): the cells match the unpadded oracle bit
+    for bit and the padding of the output planes is not written."""
+    O = oracle
+    n, ny, pitch = 150, 110, 157
+    b = I.basin(n, 3, ny=ny)
+    go = O.Grid(n, ny, b.grid.dx, b.grid.dy, 0.0, 0.0, (0, 0, 0, 0))
+    gs = S.Grid(n, ny, b.grid.dx, b.grid.dy, 0.0, 0.0, (0, 0, 0, 0), pitch)
+    p = O.Params()
+    xc, yc, _ = b.target
+    phi = O.target(go, p, b.B, xc, yc, 80e3, O.GAUSS)
+    rng = np.random.default_rng(3)
+    q = [phi, 0.01 * rng.standard_normal(phi.shape), 0.01 * rng.standard_normal(phi.shape)]
+    _, dt = O.adj_nsub(go, p, b.B, 0.0, 3600.0, 4)
+    qc = list(q)
+    for _ in range(6):
+        qc = list(O.adj_step(go, p, b.B, *qc, dt)[:3])
+
+    def wide(a, fill=np.nan):
+        w = np.full((ny, pitch), fill)
+        w[:, :n] = a
+        return dev(w)
+    Bd = wide(b.B)
+    a = [wide(x) for x in q]
+    bb = [wide(np.zeros((ny, n)), -7.0) for _ in range(3)]
+    for _ in range(6):
+        S.adj_step(gs, S.Params(), Bd, a, bb, dt)
+        a, bb = bb, a
+    got = [host(x) for x in a]
+    for x, y in zip(got, qc):
+        assert np.array_equal(x[:, :n], y)
+    # after an even number of steps a is the input plane set again (NaN
+    # padding) and bb the output set (-7 padding): neither padding was written
+    assert all(np.isnan(x[:, n:]).all() for x in got)
+    assert all((host(x)[:, n:] == -7.0).all() for x in bb)
