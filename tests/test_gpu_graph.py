@@ -1,6 +1,6 @@
 """HIP-graph capture of the device-controlled stepping (the form the headline
-step is timed in), of the same with device-scheduled flag passes, and of a
-batched level's advance (launch per attempt, and the one persistent launch):
+step is timed in), of the same with device-scheduled flag passes, of
+adjoint steps, and of a batched level's advance (launch per attempt, and the one persistent launch):
 a graph of
 K attempts, captured once, is replayed several times with eager work and
 synchronisations in between, and the state and control block after every
@@ -170,3 +170,40 @@ def test_advance_flagged_graph_replays_match_eager(S):
         assert torch.equal(bufs["g"]["acc"], bufs["e"]["acc"]), r
         assert torch.equal(bufs["g"]["macc"], bufs["e"]["macc"]), r
     assert calls[0] >= 6 and bufs["g"]["acc"].any()
+
+
+def test_adjoint_steps_graph_replays_match_eager(S):
+    """Six adjoint steps (ping-pong between two plane sets) captured once:
+    every replay, restarted from the same target data with eager work in
+    between, equals the same steps issued eagerly, bit for bit."""
+    n, ny = 300, 200
+    b = I.basin(n, 3, ny=ny)
+    g = S.Grid(n, ny, b.grid.dx, b.grid.dy)
+    p = S.Params()
+    B = torch.tensor(b.B, **F64)
+    phi = [torch.zeros(ny, n, **F64) for _ in range(3)]
+    S.adj_target(g, p, B, b.target[0], b.target[1], 60e3, S.GAUSS, phi)
+    ea, eb = [x.clone() for x in phi], [torch.empty_like(x) for x in phi]
+    ga, gb = [x.clone() for x in phi], [torch.empty_like(x) for x in phi]
+    # a Courant number of 0.8 at the deepest cell
+    dt = 0.8 * min(b.grid.dx, b.grid.dy) / float(np.sqrt(9.81 * max(-b.B.min(), 1.0)))
+
+    def steps(a, bb, stream=None):
+        for k in range(6):
+            src, dst = (a, bb) if k % 2 == 0 else (bb, a)
+            S.adj_step(g, p, B, src, dst, dt, stream=stream)
+
+    graph = capture(lambda st: steps(ga, gb, st))
+    scratch = torch.randn(1 << 16, **F64)
+    for r in range(3):
+        for x, y, z in zip(ea, ga, phi):
+            x.copy_(z)
+            y.copy_(z)
+        steps(ea, eb)
+        torch.cuda.synchronize()
+        graph.replay()
+        scratch.mul_(1.0001).add_(float(r))
+        torch.cuda.synchronize()
+        for x, y in zip(ga, ea):
+            assert torch.equal(x, y), r
+    assert bool(torch.isfinite(ea[0]).all()) and not torch.equal(ea[0], phi[0])
