@@ -820,3 +820,30 @@ def test_adj_step_pitched_rows(oracle, S):
     # padding) and bb the output set (-7 padding): neither padding was written
     assert all(np.isnan(x[:, n:]).all() for x in got)
     assert all((host(x)[:, n:] == -7.0).all() for x in bb)
+
+
+def test_surface_flag_parity_pitched_rows(oracle, S):
+    """Surface flags on rows padded to a pitch above nx: the cells equal the
+    oracle's and the padding of the flag planes is not written."""
+    O = oracle
+    rng = np.random.default_rng(22)
+    nx, ny, pitch = 203, 67, 211
+    B = -rng.uniform(-20.0, 300.0, (ny, nx))
+    h = np.maximum(0.0, rng.normal(0, 0.3, (ny, nx)) - B)
+    go = O.Grid(nx, ny, 100.0, 100.0, 0.0, 0.0, (0, 0, 0, 0))
+    gs = S.Grid(nx, ny, 100.0, 100.0, 0.0, 0.0, (0, 0, 0, 0), pitch)
+
+    def wide(a):
+        w = np.full((ny, pitch), np.nan)
+        w[:, :nx] = a
+        return dev(w)
+    acc_c = np.zeros((ny, nx), np.int8)
+    fl_c = O.surface_flag(go, O.Params(), O.NONLINEAR, B, h, 0.05, acc_c)
+    fl_g = torch.full((ny, pitch), 5, dtype=torch.int8, device=DEV)
+    acc_g = torch.zeros(ny, pitch, dtype=torch.int8, device=DEV)
+    S.swe_surface_flag(gs, S.Params(), wide(B), [wide(h), wide(np.zeros((ny, nx))), wide(np.zeros((ny, nx)))],
+                       0.05, fl_g, acc_g)
+    fg, ag = host(fl_g), host(acc_g)
+    assert np.array_equal(fg[:, :nx], fl_c) and np.array_equal(ag[:, :nx], acc_c)
+    assert (fg[:, nx:] == 5).all() and not ag[:, nx:].any()
+    assert fl_c.any() and not fl_c.all()
